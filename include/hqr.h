@@ -1,0 +1,185 @@
+/*
+ * hqr.h -- C ABI of the MI355X (gfx950) tiled hierarchical Householder QR.
+ *
+ * The library factors a dense double-precision M x N matrix (M >= N) with the
+ * tiled QR algorithms of Dongarra, Faverge, Herault, Langou and Robert,
+ * "Hierarchical QR factorization algorithms for multi-core cluster systems":
+ * the matrix is cut into b x b tiles, every tile below the diagonal is zeroed
+ * by an elimination elim(i, killer(i,k), k) (Section II, Algorithm 1), each
+ * elimination runs as tile kernels GEQRT/UNMQR + TSQRT/TSMQR or TTQRT/TTMQR
+ * (Algorithm 2), and the order of eliminations -- the elimination list -- is
+ * produced by the reduction trees of Section III and their hierarchical
+ * composition of Section IV.  All kernels of one factorization run inside a
+ * single persistent GPU launch that fires each task when its input tiles are
+ * ready (Section IV-B, "Execution scheme").
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major with a leading dimension (LAPACK layout):
+ *     element (r, c) of A is dA[r + c * lda].
+ *   - Device pointers are HIP device memory of the current device; the caller
+ *     owns them.  Host pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls that take a stream only enqueue work on it and return before the
+ *     GPU has finished; results are valid once the stream is synchronized.
+ *   - Return value 0 is success.  A negative value -i means argument i
+ *     (1-based) is invalid and nothing was enqueued.  Positive values are
+ *     runtime failures (see hqr_strerror).  No C++ exception crosses the ABI.
+ */
+#ifndef HQR_H_
+#define HQR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Reduction-tree kinds (Section III: flat tree / Sameh-Kuck, binary tree,
+ * Greedy; Fibonacci is named in Sections III-C and V; CHAIN is the "domino"
+ * coupling tree of Section IV-B). */
+enum {
+  HQR_FLAT = 0,
+  HQR_BINARY = 1,
+  HQR_GREEDY = 2,
+  HQR_FIBONACCI = 3,
+  HQR_CHAIN = 4
+};
+
+/* Elimination kinds (Section II: TS = triangle on top of square, TT =
+ * triangle on top of triangle). */
+enum { HQR_KIND_TS = 0, HQR_KIND_TT = 1 };
+
+/* Runtime error codes (positive). */
+enum {
+  HQR_ERR_HIP = 1,        /* a HIP runtime call failed */
+  HQR_ERR_WATCHDOG = 2,   /* a task waited longer than the spin limit; results are invalid */
+  HQR_ERR_WORKSPACE = 3,  /* workspace too small */
+  HQR_ERR_NOMEM = 4,      /* host or device allocation for the task plan failed */
+  HQR_ERR_INTERNAL = 5,   /* internal inconsistency (bug) */
+  HQR_ERR_INVALID_LIST = 6 /* an elimination list breaks the rules of Section II */
+};
+
+/* Parameters of the hierarchical algorithm (Section IV-A and V-A).
+ *   nb        tile size b: 64, 128 or 256.
+ *   ib        inner blocking of the tile kernels; must be 16.
+ *   p         virtual clusters of the cyclic row mapping (>= 1): row i goes to
+ *             cluster i mod p with local index i / p.
+ *   a         TS domain size in tiles (>= 1); a = 1 means TT kernels only,
+ *             a >= number of tile rows with p = 1 is the flat tree with TS
+ *             kernels.
+ *   low       level-1 tree inside a cluster (FLAT, BINARY, GREEDY, FIBONACCI).
+ *   high      level-3 tree over the p top tiles of a panel (same choices).
+ *   coupling  level-2 tree (CHAIN is the domino scheme; any tree is allowed).
+ *   domino    1 = coupling level on, 0 = off. */
+typedef struct hqr_params {
+  int32_t nb;
+  int32_t ib;
+  int32_t p;
+  int32_t a;
+  int32_t low;
+  int32_t high;
+  int32_t coupling;
+  int32_t domino;
+} hqr_params;
+
+/* Execution controls of the persistent scheduler (not part of the algorithm).
+ *   workers     persistent workgroups; 0 = one per free slot on the device
+ *               (2 per compute unit); 1 = one workgroup that runs the tasks
+ *               strictly in list order.  Any value gives bitwise identical
+ *               results.
+ *   order       0 = tasks are handed out by a critical-path priority order
+ *               (a topological order of the task graph); 1 = in the canonical
+ *               program order of Algorithm 2.
+ *   spin_limit  polls of one dependency counter before the kernel gives up and
+ *               reports HQR_ERR_WATCHDOG; 0 = a built-in limit of about a
+ *               minute of polling. */
+typedef struct hqr_exec {
+  int32_t workers;
+  int32_t order;
+  int64_t spin_limit;
+} hqr_exec;
+
+/* One elimination elim(victim, killer, k) (Section II).  `level` is the
+ * hierarchical level 0..3 of Section IV-B (0 = TS domain, 1 = low tree,
+ * 2 = coupling, 3 = high tree); `round` is the round of the tree that
+ * produced it (the unit-time step for Greedy). */
+typedef struct hqr_elim {
+  int32_t k, victim, killer, kind, level, round;
+} hqr_elim;
+
+/* Summary of the kernel task graph of an elimination list (Algorithm 2). */
+typedef struct hqr_dag_info {
+  int64_t eliminations;   /* records in the list */
+  int64_t tasks;          /* GEQRT+UNMQR+TSQRT+TSMQR+TTQRT+TTMQR tasks (unsplit) */
+  int64_t count[6];       /* per kernel, in that order */
+  int64_t weight;         /* sum of kernel weights in units of b^3/3 flops */
+  int64_t critical_path;  /* longest weighted path through the task graph */
+  int64_t device_tasks;   /* tasks after column-chunk splitting of the updates */
+} hqr_dag_info;
+
+/* Elimination list of the hierarchical algorithm (Sections III and IV) for a
+ * matrix of mt x nt tiles, in canonical order: panel by panel; inside a
+ * panel level 0 by (cluster, killer, victim), levels 1 and 2 by (cluster,
+ * round, victim), level 3 by (round, victim).
+ *   out    host array of `cap` records, or NULL to only count.
+ *   count  receives the number of records (sum over k < min(mt,nt) of
+ *          mt - k - 1).
+ * Errors: -1/-2 if mt or nt < 1, -3 for bad params, -5 if out != NULL and
+ * cap is too small (count is still set). */
+int hqr_elimlist(int32_t mt, int32_t nt, const hqr_params* params, hqr_elim* out, int64_t cap,
+                 int64_t* count);
+
+/* Check a host elimination list against the rules of Section II: every tile
+ * (i,k) below the diagonal killed exactly once; when elim(i, piv, k) runs,
+ * rows i and piv are zero in every panel k' < k and piv is not yet killed in
+ * panel k; a TS victim is never a killer in its panel.  Returns 0 if valid,
+ * HQR_ERR_INVALID_LIST otherwise, -1..-4 for bad arguments. */
+int hqr_elimlist_validate(int32_t mt, int32_t nt, const hqr_elim* list, int64_t count);
+
+/* Task-graph summary for (mt, nt, params) (Algorithm 2 expansion; weights of
+ * Section II: GEQRT 4, UNMQR 6, TSQRT 6, TSMQR 12, TTQRT 2, TTMQR 6). */
+int hqr_dag_stats(int32_t mt, int32_t nt, const hqr_params* params, hqr_dag_info* out);
+
+/* Bytes of device workspace hqr_factor needs for an M x N matrix: the T
+ * factors of every tile kernel, the per-tile dependency counters, a status
+ * word and, when M or N is not a multiple of nb, a zero-padded copy of A. */
+int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* bytes);
+
+/* QR factorization A = Q R (Section II; the result is the Householder QR of
+ * the whole matrix, reached through the elimination list of `params`).
+ *   dA      device, M x N, lda >= M; overwritten: R in the upper triangle of
+ *           the leading N x N block, Householder vectors of every tile kernel
+ *           elsewhere.  Q is never formed.
+ *   M >= N >= 1.
+ *   dwork   device workspace of at least hqr_workspace_size bytes; it holds
+ *           the T factors, so keep it unchanged while the factorization is
+ *           used (hqr_apply_qt).
+ *   exec    NULL for defaults.
+ * Errors: -2 if M < N or M < 1, -3 if N < 1, -4 if lda < M, -5 bad params,
+ * -7 workspace too small.  Runtime failures inside the launch (watchdog) are
+ * reported by hqr_status.  The first call for a given (tile grid, params,
+ * exec.order) builds the task plan on the host and uploads it to device
+ * memory owned by the library (kept until hqr_release_plans). */
+int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params,
+               const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
+
+/* Status word of the last factorization run in `dwork`: synchronizes the
+ * stream, then reports 0 or HQR_ERR_WATCHDOG in *status. */
+int hqr_status(const void* dwork, void* stream, int32_t* status);
+
+/* Free every cached task plan (host and device).  Not thread-safe with
+ * respect to concurrent hqr_factor calls. */
+void hqr_release_plans(void);
+
+/* Message for an error code. */
+const char* hqr_strerror(int code);
+
+/* Library version string. */
+const char* hqr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HQR_H_ */

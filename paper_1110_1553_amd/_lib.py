@@ -1,0 +1,143 @@
+"""ctypes binding of ``libhqr.so`` (argument marshalling only).
+
+Every function here forwards to the C ABI declared in ``include/hqr.h``;
+no step of the factorization runs in Python.  Importing this module fails
+loudly when the HIP library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhqr.so")
+
+FLAT, BINARY, GREEDY, FIBONACCI, CHAIN = 0, 1, 2, 3, 4
+TREES = {"flat": FLAT, "binary": BINARY, "greedy": GREEDY, "fibonacci": FIBONACCI, "chain": CHAIN}
+OPS = ("GEQRT", "UNMQR", "TSQRT", "TSMQR", "TTQRT", "TTMQR")
+
+ERR_WATCHDOG = 2
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("nb", "ib", "p", "a", "low", "high", "coupling", "domino")]
+
+
+class Exec(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("order", ctypes.c_int32), ("spin_limit", ctypes.c_int64)]
+
+
+class Elim(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("k", "victim", "killer", "kind", "level", "round")]
+
+
+class DagInfo(ctypes.Structure):
+    _fields_ = [("eliminations", ctypes.c_int64), ("tasks", ctypes.c_int64), ("count", ctypes.c_int64 * 6),
+                ("weight", ctypes.c_int64), ("critical_path", ctypes.c_int64), ("device_tasks", ctypes.c_int64)]
+
+
+EXPORTS = ("hqr_elimlist", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size", "hqr_factor",
+           "hqr_status", "hqr_release_plans", "hqr_strerror", "hqr_version")
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhqr.so is not built (%s); run __graft_entry__.build() first" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    P = ctypes.POINTER
+    lib.hqr_elimlist.argtypes = [i32, i32, P(Params), P(Elim), i64, P(i64)]
+    lib.hqr_elimlist_validate.argtypes = [i32, i32, P(Elim), i64]
+    lib.hqr_dag_stats.argtypes = [i32, i32, P(Params), P(DagInfo)]
+    lib.hqr_workspace_size.argtypes = [i64, i64, P(Params), P(ctypes.c_size_t)]
+    lib.hqr_factor.argtypes = [vp, i64, i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
+    lib.hqr_status.argtypes = [vp, vp, P(i32)]
+    lib.hqr_release_plans.argtypes = []
+    lib.hqr_release_plans.restype = None
+    lib.hqr_strerror.argtypes = [ctypes.c_int]
+    lib.hqr_strerror.restype = ctypes.c_char_p
+    lib.hqr_version.argtypes = []
+    lib.hqr_version.restype = ctypes.c_char_p
+    for name in ("hqr_elimlist", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size", "hqr_factor",
+                 "hqr_status"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class HQRError(RuntimeError):
+    def __init__(self, fn, code):
+        msg = load().hqr_strerror(code).decode()
+        super().__init__("%s failed with code %d (%s)" % (fn, code, msg))
+        self.code = code
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise HQRError(fn, rc)
+
+
+def make_params(nb=256, p=1, a=1, low="greedy", high="flat", coupling="chain", domino=0, ib=16) -> Params:
+    t = lambda x: TREES[x] if isinstance(x, str) else int(x)  # noqa: E731
+    return Params(nb, ib, p, a, t(low), t(high), t(coupling), int(domino))
+
+
+def make_exec(workers=0, order=0, spin_limit=0) -> Exec:
+    return Exec(workers, order, spin_limit)
+
+
+def elimlist(mt: int, nt: int, params: Params) -> np.ndarray:
+    lib = load()
+    n = ctypes.c_int64()
+    _check("hqr_elimlist", lib.hqr_elimlist(mt, nt, ctypes.byref(params), None, 0, ctypes.byref(n)))
+    out = (Elim * max(n.value, 1))()
+    _check("hqr_elimlist", lib.hqr_elimlist(mt, nt, ctypes.byref(params), out, n.value, ctypes.byref(n)))
+    arr = np.frombuffer(out, dtype=np.int32).reshape(-1, 6)[: n.value].copy()
+    return arr
+
+
+def validate(mt: int, nt: int, records) -> int:
+    recs = np.ascontiguousarray(np.asarray(records, dtype=np.int32).reshape(-1, 6))
+    ptr = recs.ctypes.data_as(ctypes.POINTER(Elim)) if len(recs) else None
+    return load().hqr_elimlist_validate(mt, nt, ptr, len(recs))
+
+
+def dag_stats(mt: int, nt: int, params: Params) -> dict:
+    info = DagInfo()
+    _check("hqr_dag_stats", load().hqr_dag_stats(mt, nt, ctypes.byref(params), ctypes.byref(info)))
+    return {"eliminations": info.eliminations, "tasks": info.tasks,
+            "count": dict(zip(OPS, list(info.count))), "weight": info.weight,
+            "critical_path": info.critical_path, "device_tasks": info.device_tasks}
+
+
+def workspace_size(M: int, N: int, params: Params) -> int:
+    n = ctypes.c_size_t()
+    _check("hqr_workspace_size", load().hqr_workspace_size(M, N, ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def factor_ptr(dA: int, M: int, N: int, lda: int, params: Params, exec_: Exec, dwork: int, work_bytes: int,
+               stream: int) -> None:
+    rc = load().hqr_factor(ctypes.c_void_p(dA), M, N, lda, ctypes.byref(params),
+                           ctypes.byref(exec_) if exec_ is not None else None,
+                           ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(stream))
+    _check("hqr_factor", rc)
+
+
+def status(dwork: int, stream: int) -> int:
+    s = ctypes.c_int32()
+    _check("hqr_status", load().hqr_status(ctypes.c_void_p(dwork), ctypes.c_void_p(stream), ctypes.byref(s)))
+    return s.value
+
+
+def release_plans() -> None:
+    load().hqr_release_plans()
+
+
+def version() -> str:
+    return load().hqr_version().decode()

@@ -1,0 +1,236 @@
+// C ABI of the tiled hierarchical QR library (declared in include/hqr.h).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+
+#include "../../include/hqr.h"
+#include "elim.hpp"
+#include "task.hpp"
+
+namespace hqr {
+namespace {
+
+constexpr int64_t kDefaultSpinLimit = 20000000;  // polls of one counter (tens of seconds)
+constexpr int kCtrlWords = 64;                    // cursor, status, spare
+
+struct PlanKey {
+  int32_t mt, nt, nb, p, a, low, high, coupling, domino, order, device;
+  bool operator<(const PlanKey& o) const {
+    return std::tie(mt, nt, nb, p, a, low, high, coupling, domino, order, device) <
+           std::tie(o.mt, o.nt, o.nb, o.p, o.a, o.low, o.high, o.coupling, o.domino, o.order, o.device);
+  }
+};
+
+struct DevicePlan {
+  Plan plan;
+  DevTask* d_tasks = nullptr;
+};
+
+std::mutex g_mu;
+std::map<PlanKey, std::unique_ptr<DevicePlan>> g_plans;
+
+int chunks_for(int nb) { return nb / 64; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  int32_t mt, nt, chunks;
+  size_t ctrl, cnt, tg, tk, pad, total;
+  bool padded;
+  int64_t ldp;
+};
+
+Layout layout_for(int64_t M, int64_t N, const hqr_params& p) {
+  Layout L{};
+  L.mt = (int32_t)((M + p.nb - 1) / p.nb);
+  L.nt = (int32_t)((N + p.nb - 1) / p.nb);
+  L.chunks = chunks_for(p.nb);
+  L.padded = (M % p.nb) != 0 || (N % p.nb) != 0;
+  L.ldp = (int64_t)L.mt * p.nb;
+  const size_t tiles = (size_t)L.mt * L.nt;
+  size_t off = 0;
+  L.ctrl = off; off = align256(off + kCtrlWords * sizeof(int32_t));
+  L.cnt = off; off = align256(off + tiles * L.chunks * sizeof(int32_t));
+  L.tg = off; off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
+  L.tk = off; off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
+  L.pad = off;
+  if (L.padded) off = align256(off + (size_t)L.ldp * L.nt * p.nb * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return HQR_ERR_HIP;
+  PlanKey key{mt, nt, p.nb, p.p, p.a, p.low, p.high, p.coupling, p.domino, order, dev};
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second.get();
+    return 0;
+  }
+  std::unique_ptr<DevicePlan> dp(new DevicePlan());
+  int rc = build_plan(mt, nt, p, order, chunks_for(p.nb), dp->plan);
+  if (rc) return rc;
+  const size_t bytes = dp->plan.dev.size() * sizeof(DevTask);
+  if (bytes) {
+    if (hipMalloc(&dp->d_tasks, bytes) != hipSuccess) return HQR_ERR_NOMEM;
+    if (hipMemcpy(dp->d_tasks, dp->plan.dev.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(dp->d_tasks);
+      return HQR_ERR_HIP;
+    }
+  }
+  *out = dp.get();
+  g_plans[key] = std::move(dp);
+  return 0;
+}
+
+}  // namespace
+}  // namespace hqr
+
+using namespace hqr;
+
+extern "C" {
+
+int hqr_elimlist(int32_t mt, int32_t nt, const hqr_params* params, hqr_elim* out, int64_t cap, int64_t* count) {
+  if (mt < 1) return -1;
+  if (nt < 1) return -2;
+  if (!params) return -3;
+  hqr_params p = *params;
+  p.nb = 64;  // tile size and inner blocking do not change the list
+  p.ib = 16;
+  if (check_params(p)) return -3;
+  if (!count) return -6;
+  std::vector<Elim> list = make_elimlist(mt, nt, p);
+  *count = (int64_t)list.size();
+  if (!out) return 0;
+  if (cap < (int64_t)list.size()) return -5;
+  for (size_t n = 0; n < list.size(); ++n)
+    out[n] = hqr_elim{list[n].k, list[n].victim, list[n].killer, list[n].kind, list[n].level, list[n].round};
+  return 0;
+}
+
+int hqr_elimlist_validate(int32_t mt, int32_t nt, const hqr_elim* list, int64_t count) {
+  if (mt < 1) return -1;
+  if (nt < 1) return -2;
+  if (count < 0) return -4;
+  if (!list && count > 0) return -3;
+  std::vector<Elim> v(count);
+  for (int64_t n = 0; n < count; ++n)
+    v[n] = Elim{list[n].k, list[n].victim, list[n].killer, list[n].kind, list[n].level, list[n].round};
+  return validate_elimlist(mt, nt, v.data(), count).empty() ? 0 : HQR_ERR_INVALID_LIST;
+}
+
+int hqr_dag_stats(int32_t mt, int32_t nt, const hqr_params* params, hqr_dag_info* out) {
+  if (mt < 1) return -1;
+  if (nt < 1 || nt > mt) return -2;
+  if (!params || check_params(*params)) return -3;
+  if (!out) return -4;
+  if (mt > 65535) return -1;
+  Plan plan;
+  int rc = build_plan(mt, nt, *params, 1, chunks_for(params->nb), plan);
+  if (rc) return rc;
+  *out = plan.info;
+  return 0;
+}
+
+int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* bytes) {
+  if (M < 1) return -1;
+  if (N < 1 || N > M) return -2;
+  if (!params || check_params(*params)) return -3;
+  if (!bytes) return -4;
+  *bytes = layout_for(M, N, *params).total;
+  return 0;
+}
+
+int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params, const hqr_exec* exec,
+               void* dwork, size_t work_bytes, void* stream) {
+  if (!dA) return -1;
+  if (M < 1 || M < N) return -2;
+  if (N < 1) return -3;
+  if (lda < M) return -4;
+  if (!params || check_params(*params)) return -5;
+  if (!dwork) return -7;
+  const hqr_params& p = *params;
+  const Layout L = layout_for(M, N, p);
+  if (L.mt > 65535 || L.nt > 65535) return -2;
+  if (work_bytes < L.total) return -8;
+  if (!L.padded && ((lda & 1) || ((uintptr_t)dA & 15))) {
+    // the tile kernels move two doubles per access; the padded path handles ragged shapes only
+    return (lda & 1) ? -4 : -1;
+  }
+  hqr_exec ex{0, 0, 0};
+  if (exec) ex = *exec;
+  if (ex.order != 0 && ex.order != 1) return -6;
+  DevicePlan* dp = nullptr;
+  int rc = get_plan(L.mt, L.nt, p, ex.order, &dp);
+  if (rc) return rc;
+
+  char* w = (char*)dwork;
+  LaunchArgs a{};
+  a.ctrl = (int32_t*)(w + L.ctrl);
+  a.cnt = (int32_t*)(w + L.cnt);
+  a.Tg = (double*)(w + L.tg);
+  a.Tk = (double*)(w + L.tk);
+  a.tasks = dp->d_tasks;
+  a.ntasks = (int64_t)dp->plan.dev.size();
+  a.spin_limit = ex.spin_limit > 0 ? ex.spin_limit : kDefaultSpinLimit;
+  a.mt = L.mt;
+  a.nt = L.nt;
+  a.chunks = L.chunks;
+  if (L.padded) {
+    a.A = (double*)(w + L.pad);
+    a.lda = L.ldp;
+    if ((rc = launch_zero2d(a.A, a.lda, a.lda, (int64_t)L.nt * p.nb, stream))) return rc;
+    if ((rc = launch_copy2d(dA, lda, a.A, a.lda, M, N, stream))) return rc;
+  } else {
+    a.A = dA;
+    a.lda = lda;
+  }
+  const int64_t nwords = (int64_t)((L.tg - L.ctrl) / sizeof(int32_t));  // ctrl + counters
+  if ((rc = launch_zero_i32(a.ctrl, nwords, stream))) return rc;
+  int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb);
+  if ((rc = launch_persistent(p.nb, a, workers, stream))) return rc;
+  if (L.padded && (rc = launch_copy2d(a.A, a.lda, dA, lda, M, N, stream))) return rc;
+  return 0;
+}
+
+int hqr_status(const void* dwork, void* stream, int32_t* status) {
+  if (!dwork) return -1;
+  if (!status) return -3;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return HQR_ERR_HIP;
+  int32_t ctrl[2] = {0, 0};
+  if (hipMemcpy(ctrl, dwork, sizeof(ctrl), hipMemcpyDeviceToHost) != hipSuccess) return HQR_ERR_HIP;
+  *status = ctrl[1];
+  return 0;
+}
+
+void hqr_release_plans(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (auto& kv : g_plans)
+    if (kv.second->d_tasks) (void)hipFree(kv.second->d_tasks);
+  g_plans.clear();
+}
+
+const char* hqr_strerror(int code) {
+  if (code == 0) return "success";
+  if (code < 0) return "invalid argument";
+  switch (code) {
+    case HQR_ERR_HIP: return "HIP runtime error";
+    case HQR_ERR_WATCHDOG: return "a task waited past the spin limit; results are invalid";
+    case HQR_ERR_WORKSPACE: return "workspace too small";
+    case HQR_ERR_NOMEM: return "allocation failed";
+    case HQR_ERR_INTERNAL: return "internal error";
+    case HQR_ERR_INVALID_LIST: return "elimination list breaks the validity rules";
+    default: return "unknown error";
+  }
+}
+
+const char* hqr_version(void) { return "hqr-mi355x 0.1"; }
+
+}  // extern "C"

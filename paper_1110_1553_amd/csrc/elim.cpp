@@ -1,0 +1,445 @@
+// Elimination lists (Sections III and IV of the paper) and the kernel task
+// graph of Algorithm 2, built on the host.
+#include "elim.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <queue>
+#include <sstream>
+#include <tuple>
+
+namespace hqr {
+
+// ---------------------------------------------------------------------------
+// Static trees on an ascending participant list (rows[0] survives).
+
+static void tree_flat(const std::vector<int32_t>& L, std::vector<Kill>& out) {
+  // Section III-A, Table 1: one killer, top to bottom.
+  for (size_t j = 1; j < L.size(); ++j) out.push_back({L[j], L[0], (int32_t)j});
+}
+
+static void tree_binary(const std::vector<int32_t>& L, std::vector<Kill>& out) {
+  // Section III-A, Table 4: pairs at distance 1, 2, 4, ...
+  const size_t s = L.size();
+  int32_t round = 1;
+  for (size_t d = 1; d < s; d <<= 1, ++round)
+    for (size_t j = 0; j + d < s; j += 2 * d) out.push_back({L[j + d], L[j], round});
+}
+
+static void tree_fibonacci(const std::vector<int32_t>& L, std::vector<Kill>& out) {
+  // Order-1 Fibonacci scheme: positions 1..s-1 form groups of 1, 2, 3, ...
+  // rows (last one truncated); the bottom group dies first, each group killed
+  // by the rows directly above it in natural order.
+  const int32_t s = (int32_t)L.size();
+  std::vector<std::pair<int32_t, int32_t>> groups;  // (first position, size)
+  for (int32_t pos = 1, size = 1; pos < s; pos += size, ++size) {
+    int32_t z = std::min(size, s - pos);
+    groups.push_back({pos, z});
+    if (z < size) break;
+  }
+  const int32_t G = (int32_t)groups.size();
+  for (int32_t g = 0; g < G; ++g) {
+    const int32_t first = groups[g].first, z = groups[g].second;
+    for (int32_t v = first; v < first + z; ++v) out.push_back({L[v], L[v - z], G - g});
+  }
+}
+
+static void tree_chain(const std::vector<int32_t>& L, std::vector<Kill>& out) {
+  // Domino (Section IV-B): bottom row first, each killed by the row above.
+  const int32_t s = (int32_t)L.size();
+  for (int32_t j = s - 1; j >= 1; --j) out.push_back({L[j], L[j - 1], s - j});
+}
+
+void tree_static(int kind, const std::vector<int32_t>& rows, std::vector<Kill>& out) {
+  switch (kind) {
+    case HQR_FLAT: tree_flat(rows, out); break;
+    case HQR_BINARY: tree_binary(rows, out); break;
+    case HQR_FIBONACCI: tree_fibonacci(rows, out); break;
+    case HQR_CHAIN: tree_chain(rows, out); break;
+    default: break;
+  }
+}
+
+// Greedy (Section III-B, Table 5): at step s, the rows of the panel that are
+// alive and ready (zeroed in the previous panel before step s) are counted,
+// and the bottom half of them is killed by the rows right above, pairing in
+// natural order.  `ready[r]` is the step row r was zeroed at in the previous
+// panel within the same (level, group), 0 if it was not.
+static void tree_greedy(const std::vector<int32_t>& L, const int32_t* ready, std::vector<Kill>& out,
+                        int32_t* zeroed_at) {
+  std::vector<int32_t> alive(L), avail;
+  avail.reserve(L.size());
+  for (int32_t step = 1; alive.size() > 1; ++step) {
+    avail.clear();
+    for (int32_t r : alive)
+      if ((ready ? ready[r] : 0) < step) avail.push_back(r);
+    const size_t n = avail.size(), z = n / 2;
+    if (z == 0) continue;
+    for (size_t j = 0; j < z; ++j) {
+      const int32_t victim = avail[n - z + j];
+      out.push_back({victim, avail[n - 2 * z + j], step});
+      if (zeroed_at) zeroed_at[victim] = step;
+    }
+    // the victims are the last z available rows; drop them from `alive`
+    const int32_t first_victim = avail[n - z];
+    std::vector<int32_t> keep;
+    keep.reserve(alive.size());
+    size_t vi = n - z;
+    for (int32_t r : alive) {
+      if (vi < n && r == avail[vi]) { ++vi; continue; }
+      keep.push_back(r);
+    }
+    (void)first_victim;
+    alive.swap(keep);
+  }
+}
+
+int check_params(const hqr_params& p) {
+  if (p.nb != 64 && p.nb != 128 && p.nb != 256) return -1;
+  if (p.ib != 16) return -2;
+  if (p.p < 1) return -3;
+  if (p.a < 1) return -4;
+  if (p.low < HQR_FLAT || p.low > HQR_FIBONACCI) return -5;
+  if (p.high < HQR_FLAT || p.high > HQR_FIBONACCI) return -6;
+  if (p.coupling < HQR_FLAT || p.coupling > HQR_CHAIN) return -7;
+  if (p.domino != 0 && p.domino != 1) return -8;
+  return 0;
+}
+
+namespace {
+
+// Greedy readiness per (level, group), kept for the previous and the current
+// panel.  Levels 1..3; groups are clusters (level 3 has one group).
+struct GreedyMemory {
+  int32_t mt, P;
+  std::vector<std::vector<int32_t>> prev, cur;
+  GreedyMemory(int32_t mt_, int32_t P_) : mt(mt_), P(P_), prev(3 * P_), cur(3 * P_) {}
+  void next_panel() {
+    prev.swap(cur);
+    for (auto& v : cur) v.clear();
+  }
+  void run(int kind, int level, int group, const std::vector<int32_t>& rows, std::vector<Kill>& out) {
+    if (rows.size() < 2) return;
+    if (kind != HQR_GREEDY) {
+      tree_static(kind, rows, out);
+      return;
+    }
+    const int slot = (level - 1) * P + group;
+    std::vector<int32_t>& now = cur[slot];
+    if (now.empty()) now.assign(mt, 0);
+    const std::vector<int32_t>& before = prev[slot];
+    tree_greedy(rows, before.empty() ? nullptr : before.data(), out, now.data());
+  }
+};
+
+}  // namespace
+
+// Hierarchical elimination list (Section IV-A/B).  Row i belongs to cluster
+// i mod p with local index i / p.  For panel k and cluster c, the rows of
+// the cluster at or below row k are local indices l_first..l_end-1; the top
+// tile is l_first.  With the coupling level on, the local rows on or below
+// the local diagonal (l >= k) are reduced by levels 0 and 1 into row l = k,
+// and the coupling tree reduces [top, ..., k] into the top tile; without it
+// levels 0 and 1 reduce the whole local column into the top tile.  Level 0
+// kills every row of a domain of `a` local rows (aligned on multiples of a,
+// cut at the first row) by the domain head with TS kernels; level 1 reduces
+// the domain heads with the low tree; level 3 reduces the p top tiles with
+// the high tree.
+std::vector<Elim> make_elimlist(int32_t mt, int32_t nt, const hqr_params& prm) {
+  std::vector<Elim> out;
+  const int32_t K = std::min(mt, nt), P = prm.p, a = prm.a;
+  GreedyMemory mem(mt, P);
+  struct L0 { int32_t c, killer, victim, round; };
+  struct LT { int32_t c, round, victim, killer; };
+  std::vector<L0> lv0;
+  std::vector<LT> lv1, lv2, lv3;
+  std::vector<int32_t> rows, tops;
+  std::vector<Kill> kills;
+  for (int32_t k = 0; k < K; ++k) {
+    mem.next_panel();
+    lv0.clear(); lv1.clear(); lv2.clear(); lv3.clear(); tops.clear();
+    for (int32_t c = 0; c < P; ++c) {
+      const int32_t l_first = (k <= c) ? 0 : (k - c + P - 1) / P;
+      const int32_t l_end = (mt - c + P - 1) / P;  // rows c, c+P, ... below mt
+      if (l_first >= l_end) continue;
+      auto glob = [&](int32_t l) { return l * P + c; };
+      const int32_t top = l_first;
+      tops.push_back(glob(top));
+      const int32_t s0 = prm.domino ? std::max(l_first, k) : l_first;
+      if (s0 < l_end) {
+        for (int32_t l = s0 + 1; l < l_end; ++l) {
+          const int32_t head = std::max(a * (l / a), s0);
+          if (head != l) lv0.push_back({c, glob(head), glob(l), l - head});
+        }
+        rows.clear();
+        rows.push_back(glob(s0));
+        for (int32_t l = s0 + 1; l < l_end; ++l)
+          if (l % a == 0) rows.push_back(glob(l));
+        kills.clear();
+        mem.run(prm.low, 1, c, rows, kills);
+        for (const Kill& q : kills) lv1.push_back({c, q.round, q.victim, q.killer});
+      }
+      if (prm.domino) {
+        rows.clear();
+        rows.push_back(glob(top));
+        for (int32_t l = top + 1; l <= k && l < l_end; ++l) rows.push_back(glob(l));
+        kills.clear();
+        mem.run(prm.coupling, 2, c, rows, kills);
+        for (const Kill& q : kills) lv2.push_back({c, q.round, q.victim, q.killer});
+      }
+    }
+    std::sort(tops.begin(), tops.end());
+    kills.clear();
+    mem.run(prm.high, 3, 0, tops, kills);
+    for (const Kill& q : kills) lv3.push_back({0, q.round, q.victim, q.killer});
+
+    std::sort(lv0.begin(), lv0.end(), [](const L0& x, const L0& y) {
+      return std::tie(x.c, x.killer, x.victim) < std::tie(y.c, y.killer, y.victim);
+    });
+    auto by_c_round_victim = [](const LT& x, const LT& y) {
+      return std::tie(x.c, x.round, x.victim) < std::tie(y.c, y.round, y.victim);
+    };
+    std::sort(lv1.begin(), lv1.end(), by_c_round_victim);
+    std::sort(lv2.begin(), lv2.end(), by_c_round_victim);
+    std::sort(lv3.begin(), lv3.end(), by_c_round_victim);
+    for (const L0& e : lv0) out.push_back({k, e.victim, e.killer, HQR_KIND_TS, 0, e.round});
+    for (const LT& e : lv1) out.push_back({k, e.victim, e.killer, HQR_KIND_TT, 1, e.round});
+    for (const LT& e : lv2) out.push_back({k, e.victim, e.killer, HQR_KIND_TT, 2, e.round});
+    for (const LT& e : lv3) out.push_back({k, e.victim, e.killer, HQR_KIND_TT, 3, e.round});
+  }
+  return out;
+}
+
+// Validity rules of Section II.  `zeroed[r]` counts the panels in which row r
+// has been killed so far; rows are killed panel after panel, so row r is
+// ready for panel k -- and, for a killer, still alive in it -- exactly when
+// zeroed[r] == k.
+std::string validate_elimlist(int32_t mt, int32_t nt, const Elim* list, int64_t count) {
+  std::ostringstream why;
+  const int32_t K = std::min(mt, nt);
+  std::vector<int32_t> zeroed(mt, 0);
+  std::vector<uint8_t> ts_victim((size_t)mt * K, 0);
+  for (int64_t n = 0; n < count; ++n) {
+    const Elim& e = list[n];
+    if (e.k < 0 || e.k >= K || e.victim <= e.k || e.victim >= mt || e.killer < e.k || e.killer >= mt ||
+        e.killer == e.victim || (e.kind != HQR_KIND_TS && e.kind != HQR_KIND_TT)) {
+      why << "record " << n << " out of range";
+      return why.str();
+    }
+    if (zeroed[e.victim] != e.k) {
+      why << "record " << n << ": row " << e.victim << " is not ready for panel " << e.k
+          << " or is already zero";
+      return why.str();
+    }
+    if (zeroed[e.killer] != e.k) {
+      why << "record " << n << ": killer " << e.killer << " is not ready for panel " << e.k
+          << " or is already zero";
+      return why.str();
+    }
+    zeroed[e.victim] = e.k + 1;
+    if (e.kind == HQR_KIND_TS) ts_victim[(size_t)e.victim * K + e.k] = 1;
+  }
+  for (int32_t r = 0; r < mt; ++r)
+    if (zeroed[r] != std::min(r, K)) {
+      why << "row " << r << " zeroed in " << zeroed[r] << " panels, expected " << std::min(r, K);
+      return why.str();
+    }
+  for (int64_t n = 0; n < count; ++n)
+    if (ts_victim[(size_t)list[n].killer * K + list[n].k]) {
+      why << "record " << n << ": TS victim " << list[n].killer << " used as a killer";
+      return why.str();
+    }
+  return std::string();
+}
+
+std::vector<Task> expand_tasks(int32_t mt, int32_t nt, const std::vector<Elim>& list) {
+  std::vector<Task> tasks;
+  const int32_t K = std::min(mt, nt);
+  std::vector<uint8_t> ts_victim(mt);
+  size_t n = 0;
+  for (int32_t k = 0; k < K; ++k) {
+    size_t end = n;
+    while (end < list.size() && list[end].k == k) ++end;
+    std::fill(ts_victim.begin(), ts_victim.end(), 0);
+    for (size_t q = n; q < end; ++q)
+      if (list[q].kind == HQR_KIND_TS) ts_victim[list[q].victim] = 1;
+    for (int32_t r = k; r < mt; ++r) {
+      if (ts_victim[r]) continue;
+      tasks.push_back({GEQRT, r, -1, k, -1});
+      for (int32_t j = k + 1; j < nt; ++j) tasks.push_back({UNMQR, r, -1, k, j});
+    }
+    for (size_t q = n; q < end; ++q) {
+      const Elim& e = list[q];
+      const bool ts = e.kind == HQR_KIND_TS;
+      tasks.push_back({(uint8_t)(ts ? TSQRT : TTQRT), e.victim, e.killer, k, -1});
+      for (int32_t j = k + 1; j < nt; ++j) tasks.push_back({(uint8_t)(ts ? TSMQR : TTMQR), e.victim, e.killer, k, j});
+    }
+    n = end;
+  }
+  return tasks;
+}
+
+// Device plan: split every update into `chunks` column chunks, give each
+// task the dependency-counter versions it must wait for, and order the tasks
+// for dispatch.
+//
+// Dependency model.  Each tile has one write counter per column chunk.  A
+// panel task (GEQRT/TSQRT/TTQRT) writes every chunk of its tiles; an update
+// chunk writes one chunk of its two (or one) tiles.  Tiles read but not
+// written -- the Householder vectors and T of a finished panel task -- are
+// never written again, so reads need no ordering against later writes.  A
+// task therefore waits until every counter it touches has reached the number
+// of earlier writes in program order, and bumps the counters it writes when
+// done.
+int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chunks, Plan& plan) {
+  plan = Plan();
+  plan.mt = mt;
+  plan.nt = nt;
+  plan.nb = prm.nb;
+  plan.chunks = chunks;
+  plan.list = make_elimlist(mt, nt, prm);
+  {
+    std::string why = validate_elimlist(mt, nt, plan.list.data(), (int64_t)plan.list.size());
+    if (!why.empty()) return HQR_ERR_INTERNAL;
+  }
+  const std::vector<Task> tasks = expand_tasks(mt, nt, plan.list);
+  hqr_dag_info& info = plan.info;
+  info.eliminations = (int64_t)plan.list.size();
+  info.tasks = (int64_t)tasks.size();
+  for (const Task& t : tasks) {
+    info.count[t.op]++;
+    info.weight += op_weight(t.op);
+  }
+
+  const size_t ntiles = (size_t)mt * nt;
+  std::vector<uint32_t> writes(ntiles, 0);
+  std::vector<int64_t> last_writer(ntiles * chunks, -1);
+  std::vector<DevTask> dev;
+  std::vector<int64_t> wt;  // integer weight of each device task, units of b^3/(3 chunks)
+  std::vector<int64_t> pred_off{0}, preds;
+  dev.reserve(tasks.size() * chunks);
+  auto tile = [&](int32_t r, int32_t c) { return (size_t)r * nt + c; };
+  auto add_pred = [&](int64_t p) {
+    if (p < 0) return;
+    for (int64_t q = pred_off.back(); q < (int64_t)preds.size(); ++q)
+      if (preds[q] == p) return;
+    preds.push_back(p);
+  };
+  for (const Task& t : tasks) {
+    const bool panel = (t.op == GEQRT || t.op == TSQRT || t.op == TTQRT);
+    if (panel) {
+      DevTask d{};
+      d.op = t.op;
+      d.k = (uint16_t)t.k;
+      d.j = (uint16_t)t.k;
+      const int64_t id = (int64_t)dev.size();
+      if (t.op == GEQRT) {
+        d.row = d.killer = (uint16_t)t.row;
+        const size_t x = tile(t.row, t.k);
+        d.v[0] = writes[x];
+        for (int c = 0; c < chunks; ++c) add_pred(last_writer[x * chunks + c]);
+        writes[x]++;
+        for (int c = 0; c < chunks; ++c) last_writer[x * chunks + c] = id;
+      } else {
+        d.row = (uint16_t)t.row;
+        d.killer = (uint16_t)t.killer;
+        const size_t xp = tile(t.killer, t.k), xi = tile(t.row, t.k);
+        d.v[0] = writes[xp];
+        d.v[1] = writes[xi];
+        for (int c = 0; c < chunks; ++c) {
+          add_pred(last_writer[xp * chunks + c]);
+          add_pred(last_writer[xi * chunks + c]);
+        }
+        writes[xp]++;
+        writes[xi]++;
+        for (int c = 0; c < chunks; ++c) last_writer[xp * chunks + c] = last_writer[xi * chunks + c] = id;
+      }
+      dev.push_back(d);
+      wt.push_back((int64_t)op_weight(t.op) * chunks);
+      pred_off.push_back((int64_t)preds.size());
+    } else {
+      // update: read tile (row,k) [UNMQR] or (victim,k) [TS/TT]; write (killer,j) and (row,j)
+      const size_t xv = tile(t.row, t.k), xi = tile(t.row, t.j);
+      const size_t xp = (t.op == UNMQR) ? 0 : tile(t.killer, t.j);
+      for (int c = 0; c < chunks; ++c) {
+        DevTask d{};
+        d.op = t.op;
+        d.chunk = (uint8_t)c;
+        d.row = (uint16_t)t.row;
+        d.killer = (uint16_t)(t.op == UNMQR ? t.row : t.killer);
+        d.k = (uint16_t)t.k;
+        d.j = (uint16_t)t.j;
+        d.v[0] = writes[xv];
+        add_pred(last_writer[xv * chunks]);
+        if (t.op == UNMQR) {
+          d.v[1] = writes[xi];
+          add_pred(last_writer[xi * chunks + c]);
+        } else {
+          d.v[1] = writes[xp];
+          d.v[2] = writes[xi];
+          add_pred(last_writer[xp * chunks + c]);
+          add_pred(last_writer[xi * chunks + c]);
+        }
+        const int64_t id = (int64_t)dev.size();
+        if (t.op != UNMQR) last_writer[xp * chunks + c] = id;
+        last_writer[xi * chunks + c] = id;
+        dev.push_back(d);
+        wt.push_back(op_weight(t.op));
+        pred_off.push_back((int64_t)preds.size());
+      }
+      if (t.op != UNMQR) writes[xp]++;
+      writes[xi]++;
+    }
+  }
+  const int64_t nd = (int64_t)dev.size();
+  info.device_tasks = nd;
+
+  // successors (CSR) and bottom levels: edges always point forward in program
+  // order, so a reverse sweep sees every successor before its predecessors.
+  std::vector<int64_t> nsucc(nd + 1, 0);
+  for (int64_t q = 0; q < (int64_t)preds.size(); ++q) nsucc[preds[q] + 1]++;
+  for (int64_t i = 0; i < nd; ++i) nsucc[i + 1] += nsucc[i];
+  std::vector<int64_t> succ(preds.size()), fill(nsucc.begin(), nsucc.end() - 1);
+  for (int64_t i = 0; i < nd; ++i)
+    for (int64_t q = pred_off[i]; q < pred_off[i + 1]; ++q) succ[fill[preds[q]]++] = i;
+  std::vector<int64_t> bottom(nd, 0), prio(nd, 0);
+  int64_t cp = 0;
+  for (int64_t i = nd - 1; i >= 0; --i) {
+    int64_t best = 0, bestp = 0;
+    for (int64_t q = nsucc[i]; q < nsucc[i + 1]; ++q) {
+      best = std::max(best, bottom[succ[q]]);
+      bestp = std::max(bestp, prio[succ[q]]);
+    }
+    bottom[i] = wt[i] + best;
+    // dispatch priority: panel kernels run far below their flop rate, so they
+    // count three times their weight on the path
+    const bool panel = dev[i].op == GEQRT || dev[i].op == TSQRT || dev[i].op == TTQRT;
+    prio[i] = wt[i] * (panel ? 3 : 1) + bestp;
+    cp = std::max(cp, bottom[i]);
+  }
+  info.critical_path = (cp + chunks - 1) / chunks;
+
+  if (order == 1) {
+    plan.dev.swap(dev);
+    return 0;
+  }
+  // list schedule: repeatedly take the ready task with the longest remaining path
+  std::vector<int32_t> indeg(nd, 0);
+  for (int64_t i = 0; i < nd; ++i) indeg[i] = (int32_t)(pred_off[i + 1] - pred_off[i]);
+  typedef std::pair<int64_t, int64_t> Key;  // (priority, -index)
+  std::priority_queue<Key> ready;
+  for (int64_t i = 0; i < nd; ++i)
+    if (indeg[i] == 0) ready.push({prio[i], -i});
+  plan.dev.reserve(nd);
+  while (!ready.empty()) {
+    const int64_t i = -ready.top().second;
+    ready.pop();
+    plan.dev.push_back(dev[i]);
+    for (int64_t q = nsucc[i]; q < nsucc[i + 1]; ++q)
+      if (--indeg[succ[q]] == 0) ready.push({prio[succ[q]], -succ[q]});
+  }
+  if ((int64_t)plan.dev.size() != nd) return HQR_ERR_INTERNAL;
+  return 0;
+}
+
+}  // namespace hqr

@@ -1,0 +1,84 @@
+// Host-side elimination lists and kernel task graphs.
+//
+// Elimination lists follow Sections III and IV of the paper (reduction trees
+// and their hierarchical composition); the task graph is the kernel expansion
+// of Algorithm 2 with one triangularisation per tile (the tile-state model of
+// Section II: square -> triangle -> zero).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hqr.h"
+
+namespace hqr {
+
+struct Elim {
+  int32_t k, victim, killer, kind, level, round;
+};
+
+// Reduction tree on an ascending participant list `rows` (rows[0] survives).
+// Appends (victim, killer, round) triples.
+struct Kill {
+  int32_t victim, killer, round;
+};
+
+void tree_static(int kind, const std::vector<int32_t>& rows, std::vector<Kill>& out);
+
+// Checks params; returns 0 or a negative code for the offending field.
+int check_params(const hqr_params& p);
+
+std::vector<Elim> make_elimlist(int32_t mt, int32_t nt, const hqr_params& p);
+
+// Empty string when the list obeys the rules of Section II; else a reason.
+std::string validate_elimlist(int32_t mt, int32_t nt, const Elim* list, int64_t count);
+
+enum Op : uint8_t { GEQRT = 0, UNMQR = 1, TSQRT = 2, TSMQR = 3, TTQRT = 4, TTMQR = 5 };
+
+inline int op_weight(int op) {
+  static const int w[6] = {4, 6, 6, 12, 2, 6};
+  return w[op];
+}
+
+// One kernel task of Algorithm 2.  Unused fields are -1.
+struct Task {
+  uint8_t op;
+  int32_t row;     // GEQRT/UNMQR: the tile row; TS/TT: the victim i
+  int32_t killer;  // TS/TT only
+  int32_t k;       // panel
+  int32_t j;       // updated tile column (UNMQR, TSMQR, TTMQR)
+};
+
+// Kernel tasks of a list in program order: per panel, first GEQRT(r,k) and
+// UNMQR(r,k,j>k) for every row r >= k that is not a TS victim, then each
+// elimination as TSQRT+TSMQR or TTQRT+TTMQR over j > k.
+std::vector<Task> expand_tasks(int32_t mt, int32_t nt, const std::vector<Elim>& list);
+
+// Device task record (24 bytes).  The persistent kernel waits until the
+// dependency counters of the tiles it touches reach v[0..2] and bumps the
+// counters of the tiles it writes when done.
+struct DevTask {
+  uint8_t op;
+  uint8_t chunk;   // column chunk of an update task (0 for panel tasks)
+  uint16_t row;    // GEQRT/UNMQR row, or victim
+  uint16_t killer;
+  uint16_t k;
+  uint16_t j;
+  uint16_t pad;
+  uint32_t v[3];
+};
+static_assert(sizeof(DevTask) == 24, "device task record must stay 24 bytes");
+
+struct Plan {
+  int32_t mt = 0, nt = 0, nb = 0, chunks = 1;
+  std::vector<Elim> list;
+  std::vector<DevTask> dev;  // in dispatch order
+  hqr_dag_info info{};
+};
+
+// Builds the device plan.  `order` 0 = critical-path priority order, 1 =
+// program order.  `chunks` = column chunks per update task.
+int build_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, int chunks, Plan& plan);
+
+}  // namespace hqr

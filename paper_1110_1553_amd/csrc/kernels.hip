@@ -1,0 +1,614 @@
+// Tile kernels of the tiled Householder QR and the persistent scheduler that
+// runs them, for gfx950 (CDNA4).
+//
+// The six kernels of Algorithm 2 (GEQRT, UNMQR, TSQRT, TSMQR, TTQRT, TTMQR)
+// work on b x b tiles in double precision with an inner blocking of 16:
+// a panel of 16 columns is factored column by column in LDS (Householder
+// reflectors, norms reduced across 16-lane groups), its compact-WY factor T
+// (16 x 16, upper triangular) is formed, and the block reflector
+// I - V T V^T is applied to the rest of the tile(s) with FP64 MFMA
+// (v_mfma_f64_16x16x4f64).  The update kernels apply the 16-column panels of
+// a finished factorization one after another with the V panels staged
+// through double-buffered LDS.
+//
+// Work split inside a workgroup (256 threads, 4 waves): every wave owns a
+// strip of 16 matrix columns and keeps the strip (b x 16 doubles) in
+// registers as b/16 MFMA accumulators, so the reduction V^T C over the rows
+// and the update C -= V W stay inside the wave; the waves only share the V
+// panel and T in LDS.
+//
+// Register layout of an accumulator block (16 rows x 16 columns): lane l,
+// element r holds MFMA row (l / 16) + 4 r, column l % 16.  Matrix rows are
+// assigned to MFMA rows through pi(x) = 4 (x % 4) + x / 4, so that element r
+// of lane l is matrix row 4 (l / 16) + r: each lane holds 4 consecutive rows
+// of one column and loads/stores them with two 16-byte accesses.  The same
+// permutation is applied to the reflector index of W = V^T C.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+
+#include "task.hpp"
+
+namespace hqr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+constexpr int IB = 16;      // inner blocking (columns per panel)
+constexpr int LDV = IB + 1; // LDS row stride of a staged panel (odd: no bank conflicts)
+constexpr int NT = 256;     // threads per workgroup
+
+enum Kind { K_UNM = 0, K_TS = 1, K_TT = 2 };
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ d4 ld4(const double* p) {
+  const d2 x = *reinterpret_cast<const d2*>(p);
+  const d2 y = *reinterpret_cast<const d2*>(p + 2);
+  d4 r;
+  r.x = x.x; r.y = x.y; r.z = y.x; r.w = y.y;
+  return r;
+}
+
+__device__ __forceinline__ void st4(double* p, d4 v) {
+  d2 x, y;
+  x.x = v.x; x.y = v.y; y.x = v.z; y.y = v.w;
+  *reinterpret_cast<d2*>(p) = x;
+  *reinterpret_cast<d2*>(p + 2) = y;
+}
+
+__device__ __forceinline__ double sum16(double v) {
+  v += __shfl_xor(v, 1, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 8, 16);
+  return v;
+}
+
+template <int NB>
+struct Smem {
+  double V[2][NB * LDV];  // staged V panels (row-major, stride LDV)
+  double T[2][IB * LDV];  // staged T blocks
+  double R[IB * LDV];     // diagonal block of the killer's R (TS/TT panel kernels)
+  double tau[IB];
+  int task;
+};
+
+// Lane coordinates.
+struct Lane {
+  int wave, g, q, pq;
+  __device__ Lane() {
+    const int t = threadIdx.x;
+    wave = t >> 6;
+    g = (t >> 4) & 3;
+    q = t & 15;
+    pq = 4 * (q & 3) + (q >> 2);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Block-reflector application of one panel to one 16-column strip held by a
+// wave.  `acc` holds rows 0..NB-1 of the strip of the matrix the reflectors
+// act on below the identity part (C2 for TS/TT, C itself for UNM).  `c1` is
+// the strip of the killer tile (rows 16p..16p+15) for TS/TT, or null.
+//
+//   W  = V_p^T acc (+ C1_p)      reduction over the active rows
+//   W  = T_p^T W
+//   C1_p -= W,   acc -= V_p W
+//
+// Active rows: UNM rows >= 16p (V unit lower triangular), TS all rows
+// (V dense), TT rows < 16p + 16 (V upper triangular).
+template <int NB, int KIND>
+__device__ __forceinline__ bool row_block_active(int rb, int p) {
+  return (KIND == K_UNM) ? (rb >= p) : (KIND == K_TT ? rb <= p : true);
+}
+
+// The products are issued in groups (one row block in the reduction, two in
+// the update) with the LDS operands of the next group loaded before the
+// MFMAs of the current one; scheduling barriers keep the compiler from
+// hoisting all operand loads at once, which would not fit next to the
+// accumulators.  Consecutive MFMAs never write the same accumulator.
+template <int NB, int KIND>
+__device__ __forceinline__ void apply_panel(d4 (&acc)[NB / 16], const double* __restrict__ Vs,
+                                            const double* __restrict__ Ts, int p, double* c1,
+                                            int64_t ldc, const Lane& L) {
+  constexpr int NRB = NB / 16;
+  d4 c1v = {0.0, 0.0, 0.0, 0.0};
+  if (KIND != K_UNM) c1v = ld4(c1 + 4 * L.g + (int64_t)L.q * ldc);
+  d4 w0 = {0.0, 0.0, 0.0, 0.0}, w1 = w0;
+  // ---- W = V^T acc: group rb = 4 products, alternating two partial sums
+  {
+    const double* va = Vs + 4 * L.g * LDV + L.pq;  // + (16 rb + r) * LDV
+    double a[4], an[4];
+    const int lo = (KIND == K_UNM) ? p : 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = 0.0;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+      if (rb == lo) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = va[(16 * rb + r) * LDV];
+      }
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {
+      if (row_block_active<NB, KIND>(rb, p)) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (rb + 1 < NRB && row_block_active<NB, KIND>(rb + 1, p)) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) an[r] = va[(16 * (rb + 1) + r) * LDV];
+        }
+        w0 = mfma(a[0], acc[rb][0], w0);
+        w1 = mfma(a[1], acc[rb][1], w1);
+        w0 = mfma(a[2], acc[rb][2], w0);
+        w1 = mfma(a[3], acc[rb][3], w1);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = an[r];
+      }
+    }
+  }
+  d4 w = w0 + w1;
+  if (KIND != K_UNM) w += c1v;
+  d4 w2t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) w2t = mfma(Ts[(4 * L.g + r) * LDV + L.pq], w[r], w2t);
+  if (KIND != K_UNM) st4(c1 + 4 * L.g + (int64_t)L.q * ldc, c1v - w2t);
+  const d4 wn = -w2t;
+  // ---- acc -= V W: groups of two row blocks, products interleaved
+  {
+    const double* vc = Vs + L.pq * LDV + 4 * L.g;  // + 16 rb LDV + r
+#pragma unroll
+    for (int rb = 0; rb < NRB; rb += 2) {
+      const bool act0 = row_block_active<NB, KIND>(rb, p);
+      const bool act1 = row_block_active<NB, KIND>(rb + 1, p);
+      if (act0 || act1) {
+        __builtin_amdgcn_sched_barrier(0);
+        double b0[4], b1[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          b0[r] = act0 ? vc[16 * rb * LDV + r] : 0.0;
+          b1[r] = act1 ? vc[16 * (rb + 1) * LDV + r] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (act0) acc[rb] = mfma(b0[r], wn[r], acc[rb]);
+          if (act1) acc[rb + 1] = mfma(b1[r], wn[r], acc[rb + 1]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+}
+
+template <int NB, int KIND>
+__device__ __forceinline__ void load_strip(d4 (&acc)[NB / 16], const double* base, int64_t ld, int p,
+                                           const Lane& L) {
+#pragma unroll
+  for (int rb = 0; rb < NB / 16; ++rb) {
+    const bool active = (KIND == K_UNM) ? (rb >= p) : (KIND == K_TT ? rb <= p : true);
+    if (active) acc[rb] = ld4(base + 16 * rb + 4 * L.g + (int64_t)L.q * ld);
+  }
+}
+
+template <int NB, int KIND>
+__device__ __forceinline__ void store_strip(const d4 (&acc)[NB / 16], double* base, int64_t ld, int p,
+                                            const Lane& L) {
+#pragma unroll
+  for (int rb = 0; rb < NB / 16; ++rb) {
+    const bool active = (KIND == K_UNM) ? (rb >= p) : (KIND == K_TT ? rb <= p : true);
+    if (active) st4(base + 16 * rb + 4 * L.g + (int64_t)L.q * ld, acc[rb]);
+  }
+}
+
+// Staging of V panel p (rows 0..NB-1, columns 16p..16p+15 of tile `V`) into
+// LDS with the structure of the kind: UNM unit diagonal and zeros above it
+// in the diagonal block; TT zeros below the diagonal; rows that no product
+// reads are skipped.
+template <int NB>
+struct PanelPrefetch {
+  static constexpr int PER = NB / 32;  // double2 loads per thread
+  d2 v[PER];
+  double t;
+};
+
+template <int NB, int KIND>
+__device__ __forceinline__ void prefetch_panel(PanelPrefetch<NB>& pf, const double* V, int64_t ld,
+                                               const double* Tblk, int p) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < PanelPrefetch<NB>::PER; ++it) {
+    const int e = it * NT + tid;
+    const int col = e / (NB / 2), row = 2 * (e % (NB / 2));
+    const bool needed = (KIND == K_UNM) ? (row >= 16 * p) : (KIND == K_TT ? row < 16 * p + 16 : true);
+    if (needed) pf.v[it] = *reinterpret_cast<const d2*>(V + row + (int64_t)(16 * p + col) * ld);
+  }
+  pf.t = Tblk[tid];
+}
+
+template <int NB, int KIND>
+__device__ __forceinline__ void stage_panel(const PanelPrefetch<NB>& pf, double* Vs, double* Ts, int p) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < PanelPrefetch<NB>::PER; ++it) {
+    const int e = it * NT + tid;
+    const int col = e / (NB / 2), row = 2 * (e % (NB / 2));
+    const bool needed = (KIND == K_UNM) ? (row >= 16 * p) : (KIND == K_TT ? row < 16 * p + 16 : true);
+    if (needed) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = row + h;
+        double x = pf.v[it][h];
+        const int a = r - 16 * p;  // row inside the diagonal block
+        if (a >= 0 && a < 16) {
+          if (KIND == K_UNM) x = (a == col) ? 1.0 : (a < col ? 0.0 : x);
+          if (KIND == K_TT) x = (a > col) ? 0.0 : x;
+        }
+        Vs[r * LDV + col] = x;
+      }
+    }
+  }
+  Ts[(tid & 15) * LDV + (tid >> 4)] = pf.t;
+}
+
+// ---------------------------------------------------------------------------
+// Update task: one 64-column chunk of UNMQR / TSMQR / TTMQR.
+//   V, T: the factored tile and its T (block column nb x 16).
+//   C2: tile updated below the identity part (UNM: the tile itself).
+//   C1: killer tile (TS/TT).
+template <int NB, int KIND>
+__device__ __forceinline__ void run_update(Smem<NB>& sm, const double* V, const double* T, double* C1, double* C2,
+                           int64_t ld) {
+  constexpr int NP = NB / IB;
+  const Lane L;
+  d4 acc[NB / 16];
+  const int64_t coloff = (int64_t)(16 * L.wave) * ld;
+  load_strip<NB, K_TS>(acc, C2 + coloff, ld, 0, L);
+  PanelPrefetch<NB> pf;
+  prefetch_panel<NB, KIND>(pf, V, ld, T, 0);
+  for (int p = 0; p < NP; ++p) {
+    double* Vs = sm.V[p & 1];
+    double* Ts = sm.T[p & 1];
+    stage_panel<NB, KIND>(pf, Vs, Ts, p);
+    __syncthreads();
+    if (p + 1 < NP) prefetch_panel<NB, KIND>(pf, V, ld, T + (p + 1) * 256, p + 1);
+    apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p, ld, L);
+  }
+  store_strip<NB, K_TS>(acc, C2 + coloff, ld, 0, L);
+}
+
+// ---------------------------------------------------------------------------
+// Panel task: GEQRT (KIND = UNM: the tile factors itself), TSQRT (TS: the
+// triangle R on top of the square tile A), TTQRT (TT: the triangle R on top
+// of the triangle A).  `A` is the tile zeroed (or triangularised for GEQRT),
+// `R` the killer tile (TS/TT).  T blocks go to `T`.
+//
+// Column j of panel p: head = the diagonal entry of the triangle on top
+// (GEQRT: A(j,j); TS/TT: R(j,j)), tail = the entries of the column that the
+// reflector zeroes (GEQRT: A(j+1:nb, j); TS: A(0:nb, j); TT: A(0:j+1, j)).
+// With alpha = head and s = ||tail||: s = 0 gives tau = 0 (H = I);
+// otherwise beta = -sign(alpha) sqrt(alpha^2 + s^2), tau = (beta - alpha)/beta,
+// tail /= (alpha - beta), head = beta.
+template <int NB, int KIND>
+__device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, double* T, int64_t ld) {
+  constexpr int NP = NB / IB;
+  const int tid = threadIdx.x;
+  const Lane L;
+  const int cc = tid >> 4;   // column of the panel this thread updates
+  const int rq = tid & 15;   // it handles rows r with r % 16 == rq
+  double* Vs = sm.V[0];
+  double* Ts = sm.T[0];
+  double* Rs = sm.R;
+  for (int p = 0; p < NP; ++p) {
+    const int c0 = 16 * p;
+    // ---- load the panel (masked) and, for TS/TT, the diagonal block of R
+    const int rlo = (KIND == K_UNM) ? c0 : 0;
+    const int rhi = (KIND == K_TT) ? c0 + 16 : NB;
+    for (int e = tid; e < NB * 16; e += NT) {
+      const int col = e / NB, row = e % NB;
+      if (row >= rlo && row < rhi) {
+        double x = A[row + (int64_t)(c0 + col) * ld];
+        if (KIND == K_TT && row > c0 + col) x = 0.0;  // the stored GEQRT reflectors, not R
+        Vs[row * LDV + col] = x;
+      }
+    }
+    if (KIND != K_UNM) {
+      const int a = tid & 15, b = tid >> 4;
+      const double x = R[(c0 + a) + (int64_t)(c0 + b) * ld];
+      Rs[a * LDV + b] = (a <= b) ? x : 0.0;
+    }
+    __syncthreads();
+    // ---- unblocked factorization of the panel
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = c0 + jj;
+      const int tlo = (KIND == K_UNM) ? j + 1 : 0;
+      const int thi = (KIND == K_TT) ? j + 1 : NB;
+      double* headp = (KIND == K_UNM) ? &Vs[j * LDV] : &Rs[jj * LDV];  // head row
+      if (cc == jj) {
+        double ss = 0.0;
+        for (int r = rq; r < NB; r += 16)
+          if (r >= tlo && r < thi) ss += Vs[r * LDV + jj] * Vs[r * LDV + jj];
+        ss = sum16(ss);
+        const double alpha = headp[jj];
+        double tau = 0.0;
+        if (ss != 0.0) {
+          double beta = sqrt(alpha * alpha + ss);
+          if (alpha >= 0.0) beta = -beta;
+          tau = (beta - alpha) / beta;
+          const double scale = 1.0 / (alpha - beta);
+          for (int r = rq; r < NB; r += 16)
+            if (r >= tlo && r < thi) Vs[r * LDV + jj] *= scale;
+          if (rq == ((KIND == K_UNM) ? (j & 15) : 0)) headp[jj] = beta;
+        }
+        if (rq == 0) sm.tau[jj] = tau;
+      }
+      __syncthreads();
+      if (cc != jj) {
+        const double tau = sm.tau[jj];
+        double d = 0.0;
+        for (int r = rq; r < NB; r += 16)
+          if (r >= tlo && r < thi) d += Vs[r * LDV + cc] * Vs[r * LDV + jj];
+        d = sum16(d);
+        if (KIND == K_UNM) d += Vs[j * LDV + cc];
+        else if (cc > jj) d += headp[cc];
+        if (cc > jj) {
+          if (tau != 0.0) {
+            const double f = tau * d;
+            for (int r = rq; r < NB; r += 16)
+              if (r >= tlo && r < thi) Vs[r * LDV + cc] -= Vs[r * LDV + jj] * f;
+            if (rq == ((KIND == K_UNM) ? (j & 15) : 0)) headp[cc] -= f;
+          }
+        } else if (rq == 0) {
+          Ts[cc * LDV + jj] = d;  // v_cc^T v_jj, consumed when T is formed
+        }
+      }
+    }
+    __syncthreads();
+    // ---- T: T(jj,jj) = tau_jj, T(0:jj, jj) = -tau_jj T(0:jj,0:jj) (V^T v_jj)(0:jj)
+    if (tid < 16) {
+      const int i = tid;
+      double trow[16];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const double tj = sm.tau[jj];
+        double s = 0.0;
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq)
+          if (qq < jj && qq >= i) s += trow[qq] * Ts[qq * LDV + jj];
+        trow[jj] = (i < jj) ? -tj * s : (i == jj ? tj : 0.0);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        Ts[i * LDV + jj] = trow[jj];
+        T[p * 256 + i + 16 * jj] = trow[jj];
+      }
+    }
+    // ---- write the factored panel back
+    for (int e = tid; e < NB * 16; e += NT) {
+      const int col = e / NB, row = e % NB;
+      bool w = row >= rlo && row < rhi;
+      if (KIND == K_TT) w = w && row <= c0 + col;
+      if (w) A[row + (int64_t)(c0 + col) * ld] = Vs[row * LDV + col];
+    }
+    if (KIND != K_UNM) {
+      const int a = tid & 15, b = tid >> 4;
+      if (a <= b) R[(c0 + a) + (int64_t)(c0 + b) * ld] = Rs[a * LDV + b];
+    }
+    __syncthreads();
+    // ---- turn the staged panel into the V used by the block update
+    if (KIND == K_UNM) {
+      const int a = tid & 15, b = tid >> 4;
+      if (a <= b) Vs[(c0 + a) * LDV + b] = (a == b) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // ---- apply the panel's block reflector to the remaining columns
+    for (int s = p + 1 + L.wave; s < NP; s += 4) {
+      d4 acc[NB / 16];
+      double* strip = A + (int64_t)(16 * s) * ld;
+      load_strip<NB, KIND>(acc, strip, ld, p, L);
+      apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * ld + c0, ld, L);
+      store_strip<NB, KIND>(acc, strip, ld, p, L);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent scheduler.  Workgroups take task indices from a global cursor
+// in dispatch order (a topological order of the task graph), wait until the
+// dependency counters of the tiles the task touches reach the versions in
+// the task record, run it, and bump the counters of the tiles it wrote.
+// Every task a workgroup waits for was taken earlier by a running
+// workgroup, so the wait always ends.
+
+__device__ __forceinline__ bool wait_counter(int32_t* c, uint32_t v, const LaunchArgs& a, int64_t& spins) {
+  if (v == 0) return true;
+  while ((uint32_t)__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
+    if (++spins > a.spin_limit) {
+      __hip_atomic_store(&a.ctrl[1], (int32_t)HQR_ERR_WATCHDOG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    if ((spins & 255) == 0 &&
+        __hip_atomic_load(&a.ctrl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+template <int NB>
+__global__ __launch_bounds__(NT, 2) void persistent_kernel(LaunchArgs a) {
+  __shared__ Smem<NB> sm;
+  const int tid = threadIdx.x;
+  const int64_t tile_stride = (int64_t)NB * 16;  // T doubles per tile
+  for (;;) {
+    if (tid == 0) sm.task = __hip_atomic_fetch_add(&a.ctrl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(sm.task);
+    if (t >= a.ntasks) break;
+    const DevTask task = a.tasks[t];
+    const int op = task.op, ch = task.chunk, i = task.row, piv = task.killer, k = task.k, j = task.j;
+    const int C = a.chunks;
+    auto ctr = [&](int r, int c, int chunk) { return a.cnt + ((int64_t)r * a.nt + c) * C + chunk; };
+    // ---- wait
+    if (tid == 0) {
+      int64_t spins = 0;
+      bool ok = true;
+      switch (op) {
+        case GEQRT:
+          for (int c = 0; c < C && ok; ++c) ok = wait_counter(ctr(i, k, c), task.v[0], a, spins);
+          break;
+        case UNMQR:
+          ok = wait_counter(ctr(i, k, 0), task.v[0], a, spins) && wait_counter(ctr(i, j, ch), task.v[1], a, spins);
+          break;
+        case TSQRT:
+        case TTQRT:
+          for (int c = 0; c < C && ok; ++c)
+            ok = wait_counter(ctr(piv, k, c), task.v[0], a, spins) && wait_counter(ctr(i, k, c), task.v[1], a, spins);
+          break;
+        default:
+          ok = wait_counter(ctr(i, k, 0), task.v[0], a, spins) && wait_counter(ctr(piv, j, ch), task.v[1], a, spins) &&
+               wait_counter(ctr(i, j, ch), task.v[2], a, spins);
+          break;
+      }
+      (void)ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // ---- run
+    const int64_t ld = a.lda;
+    auto tileptr = [&](int r, int c) { return a.A + (int64_t)r * NB + (int64_t)c * NB * ld; };
+    const int64_t colchunk = (int64_t)ch * 64 * ld;
+    switch (op) {
+      case GEQRT:
+        run_panel<NB, K_UNM>(sm, tileptr(i, k), nullptr, a.Tg + ((int64_t)i * a.nt + k) * tile_stride, ld);
+        break;
+      case TSQRT:
+        run_panel<NB, K_TS>(sm, tileptr(i, k), tileptr(piv, k), a.Tk + ((int64_t)i * a.nt + k) * tile_stride, ld);
+        break;
+      case TTQRT:
+        run_panel<NB, K_TT>(sm, tileptr(i, k), tileptr(piv, k), a.Tk + ((int64_t)i * a.nt + k) * tile_stride, ld);
+        break;
+      case UNMQR:
+        run_update<NB, K_UNM>(sm, tileptr(i, k), a.Tg + ((int64_t)i * a.nt + k) * tile_stride, nullptr,
+                              tileptr(i, j) + colchunk, ld);
+        break;
+      case TSMQR:
+        run_update<NB, K_TS>(sm, tileptr(i, k), a.Tk + ((int64_t)i * a.nt + k) * tile_stride,
+                             tileptr(piv, j) + colchunk, tileptr(i, j) + colchunk, ld);
+        break;
+      default:
+        run_update<NB, K_TT>(sm, tileptr(i, k), a.Tk + ((int64_t)i * a.nt + k) * tile_stride,
+                             tileptr(piv, j) + colchunk, tileptr(i, j) + colchunk, ld);
+        break;
+    }
+    // ---- release
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      auto bump = [&](int32_t* c) { __hip_atomic_fetch_add(c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+      switch (op) {
+        case GEQRT:
+          for (int c = 0; c < C; ++c) bump(ctr(i, k, c));
+          break;
+        case UNMQR:
+          bump(ctr(i, j, ch));
+          break;
+        case TSQRT:
+        case TTQRT:
+          for (int c = 0; c < C; ++c) {
+            bump(ctr(piv, k, c));
+            bump(ctr(i, k, c));
+          }
+          break;
+        default:
+          bump(ctr(piv, j, ch));
+          bump(ctr(i, j, ch));
+          break;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers.
+
+__global__ void zero_i32_kernel(int32_t* p, int64_t n) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+    p[x] = 0;
+}
+
+__global__ void copy2d_kernel(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t m, int64_t n) {
+  const int64_t total = m * n;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = x % m, c = x / m;
+    dst[r + c * ldd] = src[r + c * lds];
+  }
+}
+
+__global__ void zero2d_kernel(double* dst, int64_t ldd, int64_t m, int64_t n) {
+  const int64_t total = m * n;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = x % m, c = x / m;
+    dst[r + c * ldd] = 0.0;
+  }
+}
+
+static int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+int launch_zero_i32(int32_t* p, int64_t n, void* stream) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, p, n);
+  return hipGetLastError() == hipSuccess ? 0 : HQR_ERR_HIP;
+}
+
+int launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t m, int64_t n, void* stream) {
+  if (m <= 0 || n <= 0) return 0;
+  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(m * n)), dim3(256), 0, (hipStream_t)stream, src, lds, dst, ldd, m, n);
+  return hipGetLastError() == hipSuccess ? 0 : HQR_ERR_HIP;
+}
+
+int launch_zero2d(double* dst, int64_t ldd, int64_t m, int64_t n, void* stream) {
+  if (m <= 0 || n <= 0) return 0;
+  hipLaunchKernelGGL(zero2d_kernel, dim3(grid_for(m * n)), dim3(256), 0, (hipStream_t)stream, dst, ldd, m, n);
+  return hipGetLastError() == hipSuccess ? 0 : HQR_ERR_HIP;
+}
+
+template <int NB>
+static int occupancy_workers() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_kernel<NB>, NT, 0) != hipSuccess || per < 1)
+    per = 1;
+  return cus * per;
+}
+
+int default_workers(int nb) {
+  switch (nb) {
+    case 64: return occupancy_workers<64>();
+    case 128: return occupancy_workers<128>();
+    default: return occupancy_workers<256>();
+  }
+}
+
+int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream) {
+  if (workers < 1) workers = 1;
+  hipStream_t s = (hipStream_t)stream;
+  switch (nb) {
+    case 64: hipLaunchKernelGGL(persistent_kernel<64>, dim3(workers), dim3(NT), 0, s, a); break;
+    case 128: hipLaunchKernelGGL(persistent_kernel<128>, dim3(workers), dim3(NT), 0, s, a); break;
+    case 256: hipLaunchKernelGGL(persistent_kernel<256>, dim3(workers), dim3(NT), 0, s, a); break;
+    default: return HQR_ERR_INTERNAL;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : HQR_ERR_HIP;
+}
+
+}  // namespace hqr

@@ -16,3 +16,24 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def golden_dir():
     return os.path.join(ROOT, "tests", "golden")
+
+
+@pytest.fixture(scope="session")
+def hqr_lib():
+    """The built HIP library (built once if it is missing)."""
+    from paper_1110_1553_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1110_1553_amd import build
+
+        build.build()
+    return _lib.load()
+
+
+@pytest.fixture(scope="session")
+def cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    return torch.device("cuda:0")

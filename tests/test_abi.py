@@ -1,0 +1,63 @@
+"""The C ABI: the library loads on a machine without a GPU and exports every
+function declared in include/hqr.h; argument checks reject bad input without
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "hqr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hqr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("hqr_factor", "hqr_elimlist", "hqr_workspace_size", "hqr_status"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(hqr_lib):
+    for name in declared_functions():
+        assert hasattr(hqr_lib, name), name
+        assert ctypes.cast(getattr(hqr_lib, name), ctypes.c_void_p).value
+
+
+def test_binding_covers_the_header(hqr_lib):
+    from paper_1110_1553_amd import _lib
+
+    assert sorted(_lib.EXPORTS) == declared_functions()
+
+
+def test_argument_checks_do_not_touch_the_device(hqr_lib):
+    import paper_1110_1553_amd as h
+    from paper_1110_1553_amd import _lib
+
+    p = h.make_params(nb=64, a=100)
+    # M < N, lda < M, bad tile size, bad inner blocking: rejected before any HIP call
+    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 100, 200, 100, ctypes.byref(p), None, ctypes.c_void_p(16), 1 << 30, None) == -2
+    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 200, 100, 100, ctypes.byref(p), None, ctypes.c_void_p(16), 1 << 30, None) == -4
+    bad = h.make_params(nb=96)
+    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 256, 128, 256, ctypes.byref(bad), None, ctypes.c_void_p(16), 1 << 30, None) == -5
+    bad = h.make_params(nb=64, ib=32)
+    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 256, 128, 256, ctypes.byref(bad), None, ctypes.c_void_p(16), 1 << 30, None) == -5
+    # workspace too small
+    need = h.workspace_size(256, 128, p)
+    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 256, 128, 256, ctypes.byref(p), None, ctypes.c_void_p(16), need - 1, None) == -8
+    with pytest.raises(h.HQRError):
+        h.workspace_size(10, 20, p)
+    assert _lib.load().hqr_strerror(2).decode().startswith("a task waited")
+
+
+def test_workspace_grows_for_ragged_shapes(hqr_lib):
+    import paper_1110_1553_amd as h
+
+    p = h.make_params(nb=64)
+    aligned = h.workspace_size(512, 256, p)
+    ragged = h.workspace_size(500, 250, p)
+    assert ragged >= aligned + 512 * 256 * 8
