@@ -57,7 +57,8 @@ enum {
   HQR_ERR_WORKSPACE = 3,  /* workspace too small */
   HQR_ERR_NOMEM = 4,      /* host or device allocation for the task plan failed */
   HQR_ERR_INTERNAL = 5,   /* internal inconsistency (bug) */
-  HQR_ERR_INVALID_LIST = 6 /* an elimination list breaks the rules of Section II */
+  HQR_ERR_INVALID_LIST = 6, /* an elimination list breaks the rules of Section II */
+  HQR_ERR_TIMEOUT = 7       /* hqr_status_ex: the stream did not finish in time */
 };
 
 /* Parameters of the hierarchical algorithm (Section IV-A and V-A).
@@ -91,9 +92,10 @@ typedef struct hqr_params {
  *   order       0 = tasks are handed out by a critical-path priority order
  *               (a topological order of the task graph); 1 = in the canonical
  *               program order of Algorithm 2.
- *   spin_limit  polls of one dependency counter before the kernel gives up and
- *               reports HQR_ERR_WATCHDOG; 0 = a built-in limit of about a
- *               minute of polling. */
+ *   spin_limit  polls of the dependency counters of one task before the
+ *               launch is aborted (every workgroup stops taking tasks) and
+ *               HQR_ERR_WATCHDOG is reported; 0 = a built-in limit of a few
+ *               seconds of polling. */
 typedef struct hqr_exec {
   int32_t workers;
   int32_t order;
@@ -141,6 +143,31 @@ int hqr_elimlist_validate(int32_t mt, int32_t nt, const hqr_elim* list, int64_t 
  * Section II: GEQRT 4, UNMQR 6, TSQRT 6, TSMQR 12, TTQRT 2, TTMQR 6). */
 int hqr_dag_stats(int32_t mt, int32_t nt, const hqr_params* params, hqr_dag_info* out);
 
+/* One task of the persistent launch, as the device reads it.  op: 0 GEQRT,
+ * 1 UNMQR, 2 TSQRT, 3 TSMQR, 4 TTQRT, 5 TTMQR (Algorithm 2).  `chunk` is the
+ * 64-column chunk of an update task (tile columns are split into nb/64
+ * chunks).  `row` is the tile row of GEQRT/UNMQR or the victim of a kill,
+ * `killer` the killer row (= row for GEQRT/UNMQR), `k` the panel, `j` the
+ * updated tile column (= k for panel tasks).  Before running, the task waits
+ * until the dependency counters of the tiles it touches reach v[0..2]:
+ *   GEQRT  every chunk of (row,k) >= v0
+ *   UNMQR  (row,k) chunk 0 >= v0, (row,j) chunk `chunk` >= v1
+ *   TSQRT/TTQRT  every chunk of (killer,k) >= v0 and of (row,k) >= v1
+ *   TSMQR/TTMQR  (row,k) chunk 0 >= v0, (killer,j) and (row,j) chunk
+ *                `chunk` >= v1 and v2
+ * and afterwards bumps by one the counters of the tiles (chunks) it wrote. */
+typedef struct hqr_task {
+  uint8_t op, chunk;
+  uint16_t row, killer, k, j, pad;
+  uint32_t v[3];
+} hqr_task;
+
+/* Task table of the persistent launch for (mt, nt, params) in dispatch order
+ * (order 0: critical-path priority; 1: program order).  out may be NULL to
+ * count.  Errors: -1..-4 bad arguments, -6 cap too small. */
+int hqr_plan_tasks(int32_t mt, int32_t nt, const hqr_params* params, int32_t order, hqr_task* out, int64_t cap,
+                   int64_t* count);
+
 /* Bytes of device workspace hqr_factor needs for an M x N matrix: the T
  * factors of every tile kernel, the per-tile dependency counters, a status
  * word and, when M or N is not a multiple of nb, a zero-padded copy of A. */
@@ -164,9 +191,17 @@ int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* b
 int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params,
                const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
 
-/* Status word of the last factorization run in `dwork`: synchronizes the
- * stream, then reports 0 or HQR_ERR_WATCHDOG in *status. */
+/* Status word of the last factorization run in `dwork`: waits for the
+ * stream (at most 300 s), then reports 0 or HQR_ERR_WATCHDOG in *status.
+ * Returns HQR_ERR_TIMEOUT if the stream is still busy after the wait. */
 int hqr_status(const void* dwork, void* stream, int32_t* status);
+
+/* As hqr_status with an explicit time limit (<= 0: 300 s).  When the launch
+ * was aborted by the watchdog, detail[0..3] (if not NULL) receive the task
+ * index that gave up, the dependency counter it waited on (index into the
+ * counter array: (row * nt + col) * chunks + chunk), the count it waited for
+ * and the count it last saw. */
+int hqr_status_ex(const void* dwork, void* stream, double timeout_s, int32_t* status, int32_t* detail);
 
 /* Free every cached task plan (host and device).  Not thread-safe with
  * respect to concurrent hqr_factor calls. */
@@ -174,6 +209,10 @@ void hqr_release_plans(void);
 
 /* Message for an error code. */
 const char* hqr_strerror(int code);
+
+/* "where: message" of the last failed HIP call made by this thread inside the
+ * library (empty if none). */
+const char* hqr_last_error(void);
 
 /* Library version string. */
 const char* hqr_version(void);

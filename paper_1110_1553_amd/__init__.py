@@ -38,7 +38,7 @@ class Workspace:
         return self.buf.data_ptr()
 
 
-def factor(A, params, exec_=None, work=None, stream=None, check=True):
+def factor(A, params, exec_=None, work=None, stream=None, check=True, timeout_s=0.0):
     """In-place QR of the column-major float64 CUDA tensor ``A`` (M x N,
     strides (1, lda)).  Returns the workspace (it holds the T factors)."""
     import torch
@@ -54,9 +54,11 @@ def factor(A, params, exec_=None, work=None, stream=None, check=True):
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
     _lib.factor_ptr(A.data_ptr(), M, N, lda, params, exec_, work.ptr, work.bytes, s.cuda_stream)
     if check:
-        st = _lib.status(work.ptr, s.cuda_stream)
+        st, info = _lib.status(work.ptr, s.cuda_stream, timeout_s=timeout_s, detail=True)
         if st != 0:
-            raise HQRError("hqr_factor (device)", st)
+            err = HQRError("hqr_factor (device)", st)
+            err.detail = info
+            raise RuntimeError("%s; task %d waited on counter %d for %d, last saw %d" % ((err,) + tuple(info)))
     return work
 
 

@@ -17,6 +17,7 @@ TREES = {"flat": FLAT, "binary": BINARY, "greedy": GREEDY, "fibonacci": FIBONACC
 OPS = ("GEQRT", "UNMQR", "TSQRT", "TSMQR", "TTQRT", "TTMQR")
 
 ERR_WATCHDOG = 2
+ERR_TIMEOUT = 7
 
 
 class Params(ctypes.Structure):
@@ -36,8 +37,11 @@ class DagInfo(ctypes.Structure):
                 ("weight", ctypes.c_int64), ("critical_path", ctypes.c_int64), ("device_tasks", ctypes.c_int64)]
 
 
-EXPORTS = ("hqr_elimlist", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size", "hqr_factor",
-           "hqr_status", "hqr_release_plans", "hqr_strerror", "hqr_version")
+TASK_DTYPE = np.dtype([("op", "u1"), ("chunk", "u1"), ("row", "<u2"), ("killer", "<u2"), ("k", "<u2"),
+                       ("j", "<u2"), ("pad", "<u2"), ("v", "<u4", (3,))])
+
+EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size", "hqr_factor",
+           "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_version")
 
 _lib = None
 
@@ -46,6 +50,13 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        # PyTorch ships its own HIP runtime (same soname as ROCm's).  Loading it
+        # first makes libhqr.so bind to that copy, so that the process holds a
+        # single HIP runtime and device pointers/streams are shared.
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError("libhqr.so is not built (%s); run __graft_entry__.build() first" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
@@ -54,17 +65,21 @@ def load():
     lib.hqr_elimlist.argtypes = [i32, i32, P(Params), P(Elim), i64, P(i64)]
     lib.hqr_elimlist_validate.argtypes = [i32, i32, P(Elim), i64]
     lib.hqr_dag_stats.argtypes = [i32, i32, P(Params), P(DagInfo)]
+    lib.hqr_plan_tasks.argtypes = [i32, i32, P(Params), i32, vp, i64, P(i64)]
     lib.hqr_workspace_size.argtypes = [i64, i64, P(Params), P(ctypes.c_size_t)]
     lib.hqr_factor.argtypes = [vp, i64, i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
     lib.hqr_status.argtypes = [vp, vp, P(i32)]
+    lib.hqr_status_ex.argtypes = [vp, vp, ctypes.c_double, P(i32), P(i32)]
     lib.hqr_release_plans.argtypes = []
     lib.hqr_release_plans.restype = None
     lib.hqr_strerror.argtypes = [ctypes.c_int]
     lib.hqr_strerror.restype = ctypes.c_char_p
+    lib.hqr_last_error.argtypes = []
+    lib.hqr_last_error.restype = ctypes.c_char_p
     lib.hqr_version.argtypes = []
     lib.hqr_version.restype = ctypes.c_char_p
-    for name in ("hqr_elimlist", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size", "hqr_factor",
-                 "hqr_status"):
+    for name in ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size",
+                 "hqr_factor", "hqr_status", "hqr_status_ex"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -73,7 +88,8 @@ def load():
 class HQRError(RuntimeError):
     def __init__(self, fn, code):
         msg = load().hqr_strerror(code).decode()
-        super().__init__("%s failed with code %d (%s)" % (fn, code, msg))
+        detail = load().hqr_last_error().decode() if code == 1 else ""
+        super().__init__("%s failed with code %d (%s)%s" % (fn, code, msg, (": " + detail) if detail else ""))
         self.code = code
 
 
@@ -115,6 +131,17 @@ def dag_stats(mt: int, nt: int, params: Params) -> dict:
             "critical_path": info.critical_path, "device_tasks": info.device_tasks}
 
 
+def plan_tasks(mt: int, nt: int, params: Params, order: int = 0) -> np.ndarray:
+    """The persistent launch's task table (structured array, TASK_DTYPE)."""
+    lib = load()
+    n = ctypes.c_int64()
+    _check("hqr_plan_tasks", lib.hqr_plan_tasks(mt, nt, ctypes.byref(params), order, None, 0, ctypes.byref(n)))
+    out = np.zeros(n.value, dtype=TASK_DTYPE)
+    _check("hqr_plan_tasks", lib.hqr_plan_tasks(mt, nt, ctypes.byref(params), order, ctypes.c_void_p(out.ctypes.data),
+                                                n.value, ctypes.byref(n)))
+    return out
+
+
 def workspace_size(M: int, N: int, params: Params) -> int:
     n = ctypes.c_size_t()
     _check("hqr_workspace_size", load().hqr_workspace_size(M, N, ctypes.byref(params), ctypes.byref(n)))
@@ -129,10 +156,15 @@ def factor_ptr(dA: int, M: int, N: int, lda: int, params: Params, exec_: Exec, d
     _check("hqr_factor", rc)
 
 
-def status(dwork: int, stream: int) -> int:
+def status(dwork: int, stream: int, timeout_s: float = 0.0, detail: bool = False):
+    """Status word of the launch that last used ``dwork`` (waits at most
+    ``timeout_s`` seconds; 0 = the library default).  With ``detail`` returns
+    (status, [task, counter, expected, seen])."""
     s = ctypes.c_int32()
-    _check("hqr_status", load().hqr_status(ctypes.c_void_p(dwork), ctypes.c_void_p(stream), ctypes.byref(s)))
-    return s.value
+    d = (ctypes.c_int32 * 4)()
+    _check("hqr_status_ex", load().hqr_status_ex(ctypes.c_void_p(dwork), ctypes.c_void_p(stream), timeout_s,
+                                                 ctypes.byref(s), d))
+    return (s.value, list(d)) if detail else s.value
 
 
 def release_plans() -> None:

@@ -1,7 +1,10 @@
 // C ABI of the tiled hierarchical QR library (declared in include/hqr.h).
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdio>
+#include <cstdlib>
+#include <thread>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -32,6 +35,22 @@ struct DevicePlan {
 };
 
 std::mutex g_mu;
+int32_t* g_trace = nullptr;  // pinned host words written by the GPU when HQR_TRACE is set
+
+int32_t* trace_buffer() {
+  static bool want = [] {
+    const char* e = getenv("HQR_TRACE");
+    return e && atoi(e) != 0;
+  }();
+  if (!want) return nullptr;
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (!g_trace) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 2 * kTraceSlots * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) return nullptr;
+    g_trace = (int32_t*)p;
+  }
+  return g_trace;
+}
 std::map<PlanKey, std::unique_ptr<DevicePlan>> g_plans;
 
 int chunks_for(int nb) { return nb / 64; }
@@ -66,7 +85,7 @@ Layout layout_for(int64_t M, int64_t N, const hqr_params& p) {
 
 int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan** out) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return HQR_ERR_HIP;
+  if (int rc = record_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
   PlanKey key{mt, nt, p.nb, p.p, p.a, p.low, p.high, p.coupling, p.domino, order, dev};
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_plans.find(key);
@@ -79,10 +98,11 @@ int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan*
   if (rc) return rc;
   const size_t bytes = dp->plan.dev.size() * sizeof(DevTask);
   if (bytes) {
-    if (hipMalloc(&dp->d_tasks, bytes) != hipSuccess) return HQR_ERR_NOMEM;
-    if (hipMemcpy(dp->d_tasks, dp->plan.dev.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    if (record_hip(hipMalloc(&dp->d_tasks, bytes), "hipMalloc(task plan)")) return HQR_ERR_NOMEM;
+    if (int rc = record_hip(hipMemcpy(dp->d_tasks, dp->plan.dev.data(), bytes, hipMemcpyHostToDevice),
+                            "hipMemcpy(task plan)")) {
       (void)hipFree(dp->d_tasks);
-      return HQR_ERR_HIP;
+      return rc;
     }
   }
   *out = dp.get();
@@ -139,6 +159,24 @@ int hqr_dag_stats(int32_t mt, int32_t nt, const hqr_params* params, hqr_dag_info
   return 0;
 }
 
+int hqr_plan_tasks(int32_t mt, int32_t nt, const hqr_params* params, int32_t order, hqr_task* out, int64_t cap,
+                   int64_t* count) {
+  if (mt < 1 || mt > 65535) return -1;
+  if (nt < 1 || nt > mt) return -2;
+  if (!params || check_params(*params)) return -3;
+  if (order != 0 && order != 1) return -4;
+  if (!count) return -7;
+  Plan plan;
+  int rc = build_plan(mt, nt, *params, order, chunks_for(params->nb), plan);
+  if (rc) return rc;
+  *count = (int64_t)plan.dev.size();
+  if (!out) return 0;
+  if (cap < *count) return -6;
+  static_assert(sizeof(hqr_task) == sizeof(DevTask), "task record layouts differ");
+  std::memcpy(out, plan.dev.data(), plan.dev.size() * sizeof(DevTask));
+  return 0;
+}
+
 int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* bytes) {
   if (M < 1) return -1;
   if (N < 1 || N > M) return -2;
@@ -180,6 +218,8 @@ int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* 
   a.tasks = dp->d_tasks;
   a.ntasks = (int64_t)dp->plan.dev.size();
   a.spin_limit = ex.spin_limit > 0 ? ex.spin_limit : kDefaultSpinLimit;
+  a.trace = trace_buffer();
+  if (a.trace) std::memset(a.trace, 0, 2 * kTraceSlots * sizeof(int32_t));
   a.mt = L.mt;
   a.nt = L.nt;
   a.chunks = L.chunks;
@@ -201,12 +241,49 @@ int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* 
 }
 
 int hqr_status(const void* dwork, void* stream, int32_t* status) {
+  return hqr_status_ex(dwork, stream, 0.0, status, nullptr);
+}
+
+int hqr_status_ex(const void* dwork, void* stream, double timeout_s, int32_t* status, int32_t* detail) {
   if (!dwork) return -1;
-  if (!status) return -3;
-  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return HQR_ERR_HIP;
-  int32_t ctrl[2] = {0, 0};
-  if (hipMemcpy(ctrl, dwork, sizeof(ctrl), hipMemcpyDeviceToHost) != hipSuccess) return HQR_ERR_HIP;
+  if (!status) return -4;
+  if (timeout_s <= 0.0) timeout_s = 300.0;
+  // bounded wait: poll the stream instead of blocking in the runtime
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    hipError_t e = hipStreamQuery((hipStream_t)stream);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) return record_hip(e, "hipStreamQuery");
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (dt > timeout_s) {
+      if (g_trace) {
+        // what every traced workgroup was doing when the time ran out
+        int counts[6] = {0, 0, 0, 0, 0, 0};
+        for (int b = 0; b < kTraceSlots; ++b) {
+          const int ph = g_trace[2 * b + 1];
+          counts[(ph >= 0 && ph <= 5) ? ph : 0]++;
+        }
+        fprintf(stderr, "hqr: stream still busy after %.1f s; workgroups by phase: none %d popped %d ready %d "
+                "done %d exit %d abort %d\n", dt, counts[0], counts[1], counts[2], counts[3], counts[4], counts[5]);
+        int shown = 0;
+        for (int b = 0; b < kTraceSlots && shown < 64; ++b) {
+          const int ph = g_trace[2 * b + 1];
+          if (ph == TR_POPPED || ph == TR_READY || ph == TR_DONE) {
+            fprintf(stderr, "hqr:   wg %d task %d phase %d\n", b, g_trace[2 * b], ph);
+            ++shown;
+          }
+        }
+        fflush(stderr);
+      }
+      return HQR_ERR_TIMEOUT;
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(dt < 0.01 ? 20 : 1000));
+  }
+  int32_t ctrl[6] = {0, 0, 0, 0, 0, 0};
+  if (int rc = record_hip(hipMemcpy(ctrl, dwork, sizeof(ctrl), hipMemcpyDeviceToHost), "hipMemcpy(status)")) return rc;
   *status = ctrl[1];
+  if (detail)
+    for (int q = 0; q < 4; ++q) detail[q] = ctrl[2 + q];
   return 0;
 }
 
@@ -227,9 +304,12 @@ const char* hqr_strerror(int code) {
     case HQR_ERR_NOMEM: return "allocation failed";
     case HQR_ERR_INTERNAL: return "internal error";
     case HQR_ERR_INVALID_LIST: return "elimination list breaks the validity rules";
+    case HQR_ERR_TIMEOUT: return "the GPU work did not finish within the time limit";
     default: return "unknown error";
   }
 }
+
+const char* hqr_last_error(void) { return last_error(); }
 
 const char* hqr_version(void) { return "hqr-mi355x 0.1"; }
 

@@ -73,7 +73,8 @@ struct Smem {
   double T[2][IB * LDV];  // staged T blocks
   double R[IB * LDV];     // diagonal block of the killer's R (TS/TT panel kernels)
   double tau[IB];
-  int task;
+  int task;  // index of the task taken by the workgroup (-1: launch aborted)
+  int ok;    // 1 if the task's dependencies were met, 0 if the launch was aborted
 };
 
 // Lane coordinates.
@@ -300,6 +301,7 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
   double* Vs = sm.V[0];
   double* Ts = sm.T[0];
   double* Rs = sm.R;
+  double* Zs = sm.V[1];  // Gram entries v_i^T v_j of the panel (the second V buffer is free here)
   for (int p = 0; p < NP; ++p) {
     const int c0 = 16 * p;
     // ---- load the panel (masked) and, for TS/TT, the diagonal block of R
@@ -321,16 +323,20 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
     __syncthreads();
     // ---- unblocked factorization of the panel
     for (int jj = 0; jj < 16; ++jj) {
+      // The owners of column jj read entries that other lanes of their 16-lane
+      // group wrote in the previous step; the group is one wavefront slice, so
+      // program order inside the wave is the only ordering needed.
+      __builtin_amdgcn_wave_barrier();
       const int j = c0 + jj;
       const int tlo = (KIND == K_UNM) ? j + 1 : 0;
       const int thi = (KIND == K_TT) ? j + 1 : NB;
       double* headp = (KIND == K_UNM) ? &Vs[j * LDV] : &Rs[jj * LDV];  // head row
       if (cc == jj) {
+        const double alpha = headp[jj];  // read by every lane before the owner rewrites it
         double ss = 0.0;
         for (int r = rq; r < NB; r += 16)
           if (r >= tlo && r < thi) ss += Vs[r * LDV + jj] * Vs[r * LDV + jj];
         ss = sum16(ss);
-        const double alpha = headp[jj];
         double tau = 0.0;
         if (ss != 0.0) {
           double beta = sqrt(alpha * alpha + ss);
@@ -346,12 +352,12 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
       __syncthreads();
       if (cc != jj) {
         const double tau = sm.tau[jj];
+        // head-row term of v_jj^T column cc, read before the owner lane updates it
+        const double h = (KIND == K_UNM) ? Vs[j * LDV + cc] : (cc > jj ? headp[cc] : 0.0);
         double d = 0.0;
         for (int r = rq; r < NB; r += 16)
           if (r >= tlo && r < thi) d += Vs[r * LDV + cc] * Vs[r * LDV + jj];
-        d = sum16(d);
-        if (KIND == K_UNM) d += Vs[j * LDV + cc];
-        else if (cc > jj) d += headp[cc];
+        d = sum16(d) + h;
         if (cc > jj) {
           if (tau != 0.0) {
             const double f = tau * d;
@@ -360,12 +366,13 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
             if (rq == ((KIND == K_UNM) ? (j & 15) : 0)) headp[cc] -= f;
           }
         } else if (rq == 0) {
-          Ts[cc * LDV + jj] = d;  // v_cc^T v_jj, consumed when T is formed
+          Zs[cc * LDV + jj] = d;  // v_cc^T v_jj, consumed when T is formed
         }
       }
     }
     __syncthreads();
     // ---- T: T(jj,jj) = tau_jj, T(0:jj, jj) = -tau_jj T(0:jj,0:jj) (V^T v_jj)(0:jj)
+    //      (Schreiber-Van Loan forward recurrence, one row of T per lane)
     if (tid < 16) {
       const int i = tid;
       double trow[16];
@@ -375,7 +382,7 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
         double s = 0.0;
 #pragma unroll
         for (int qq = 0; qq < 16; ++qq)
-          if (qq < jj && qq >= i) s += trow[qq] * Ts[qq * LDV + jj];
+          if (qq < jj && qq >= i) s += trow[qq] * Zs[qq * LDV + jj];
         trow[jj] = (i < jj) ? -tj * s : (i == jj ? tj : 0.0);
       }
 #pragma unroll
@@ -422,113 +429,199 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
 // Every task a workgroup waits for was taken earlier by a running
 // workgroup, so the wait always ends.
 
-__device__ __forceinline__ bool wait_counter(int32_t* c, uint32_t v, const LaunchArgs& a, int64_t& spins) {
+// Waits until *c >= v.  Returns false when the launch has been aborted: by
+// this wait running past the spin limit (it then records the abort and what
+// it was waiting for in ctrl[1..5]) or by another workgroup's abort.
+__device__ __forceinline__ bool wait_counter(int32_t* c, uint32_t v, const LaunchArgs& a, int64_t& spins, int t) {
   if (v == 0) return true;
-  while ((uint32_t)__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
-    if (++spins > a.spin_limit) {
-      __hip_atomic_store(&a.ctrl[1], (int32_t)HQR_ERR_WATCHDOG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const uint32_t seen = (uint32_t)__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (seen >= v) return true;
+    ++spins;
+    if (spins > a.spin_limit) {
+      int32_t none = 0;
+      if (__hip_atomic_compare_exchange_strong(&a.ctrl[1], &none, (int32_t)HQR_ERR_WATCHDOG, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __hip_atomic_store(&a.ctrl[2], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.ctrl[3], (int32_t)(c - a.cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.ctrl[4], (int32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.ctrl[5], (int32_t)seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       return false;
     }
-    if ((spins & 255) == 0 &&
-        __hip_atomic_load(&a.ctrl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+    if ((spins & 63) == 0 && __hip_atomic_load(&a.ctrl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
       return false;
     __builtin_amdgcn_s_sleep(2);
   }
-  return true;
 }
 
+__device__ __forceinline__ void trace(const LaunchArgs& a, int t, int phase) {
+  if (a.trace && blockIdx.x < kTraceSlots) {
+    __hip_atomic_store(&a.trace[2 * blockIdx.x], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&a.trace[2 * blockIdx.x + 1], phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// The scheduler's shared state and the tile kernels' staging buffers live in
+// the launch's dynamic LDS.
+extern __shared__ __attribute__((aligned(16))) double hqr_lds[];
+
 template <int NB>
-__global__ __launch_bounds__(NT, 2) void persistent_kernel(LaunchArgs a) {
-  __shared__ Smem<NB> sm;
-  const int tid = threadIdx.x;
-  const int64_t tile_stride = (int64_t)NB * 16;  // T doubles per tile
-  for (;;) {
-    if (tid == 0) sm.task = __hip_atomic_fetch_add(&a.ctrl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int t = __builtin_amdgcn_readfirstlane(sm.task);
-    if (t >= a.ntasks) break;
-    const DevTask task = a.tasks[t];
+__device__ __forceinline__ Smem<NB>& smem() {
+  return *reinterpret_cast<Smem<NB>*>(hqr_lds);
+}
+
+__device__ __forceinline__ int32_t* counter(const LaunchArgs& a, int r, int c, int chunk) {
+  return a.cnt + ((int64_t)r * a.nt + c) * a.chunks + chunk;
+}
+
+// The steps of one scheduler iteration are separate, non-inlined functions
+// on purpose: each one holds the lane-divergent part of its step (the work
+// of thread 0) together with the workgroup barrier that ends it, so the loop
+// in the kernel contains only uniform control flow.  When these steps were
+// inlined, the compiler moved thread 0's tail of an iteration out of the
+// loop behind a divergent exit, and the other lanes re-ran the same task.
+
+// Takes the next task index (uniform), or -1 when every task has been
+// handed out or the launch was aborted.
+template <int NB>
+__device__ __noinline__ int take_task(const LaunchArgs& a) {
+  Smem<NB>& sm = smem<NB>();
+  if (threadIdx.x == 0) {
+    int t = -1;
+    // an aborted launch hands out no more tasks: every workgroup leaves at
+    // its next pick, so the kernel ends soon after the first time-out
+    if (__hip_atomic_load(&a.ctrl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      t = __hip_atomic_fetch_add(&a.ctrl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t >= a.ntasks) t = -1;
+    sm.task = t;
+    trace(a, t, t < 0 ? TR_EXIT : TR_POPPED);
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(sm.task);
+}
+
+// Thread 0 waits for the task's input versions; returns 1 (uniform) when
+// they were reached, 0 when the launch was aborted.
+template <int NB>
+__device__ __noinline__ int wait_task(const LaunchArgs& a, int t, const DevTask& task) {
+  Smem<NB>& sm = smem<NB>();
+  if (threadIdx.x == 0) {
     const int op = task.op, ch = task.chunk, i = task.row, piv = task.killer, k = task.k, j = task.j;
     const int C = a.chunks;
-    auto ctr = [&](int r, int c, int chunk) { return a.cnt + ((int64_t)r * a.nt + c) * C + chunk; };
-    // ---- wait
-    if (tid == 0) {
-      int64_t spins = 0;
-      bool ok = true;
-      switch (op) {
-        case GEQRT:
-          for (int c = 0; c < C && ok; ++c) ok = wait_counter(ctr(i, k, c), task.v[0], a, spins);
-          break;
-        case UNMQR:
-          ok = wait_counter(ctr(i, k, 0), task.v[0], a, spins) && wait_counter(ctr(i, j, ch), task.v[1], a, spins);
-          break;
-        case TSQRT:
-        case TTQRT:
-          for (int c = 0; c < C && ok; ++c)
-            ok = wait_counter(ctr(piv, k, c), task.v[0], a, spins) && wait_counter(ctr(i, k, c), task.v[1], a, spins);
-          break;
-        default:
-          ok = wait_counter(ctr(i, k, 0), task.v[0], a, spins) && wait_counter(ctr(piv, j, ch), task.v[1], a, spins) &&
-               wait_counter(ctr(i, j, ch), task.v[2], a, spins);
-          break;
-      }
-      (void)ok;
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // ---- run
-    const int64_t ld = a.lda;
-    auto tileptr = [&](int r, int c) { return a.A + (int64_t)r * NB + (int64_t)c * NB * ld; };
-    const int64_t colchunk = (int64_t)ch * 64 * ld;
+    int64_t spins = 0;
+    bool ok = true;
     switch (op) {
       case GEQRT:
-        run_panel<NB, K_UNM>(sm, tileptr(i, k), nullptr, a.Tg + ((int64_t)i * a.nt + k) * tile_stride, ld);
-        break;
-      case TSQRT:
-        run_panel<NB, K_TS>(sm, tileptr(i, k), tileptr(piv, k), a.Tk + ((int64_t)i * a.nt + k) * tile_stride, ld);
-        break;
-      case TTQRT:
-        run_panel<NB, K_TT>(sm, tileptr(i, k), tileptr(piv, k), a.Tk + ((int64_t)i * a.nt + k) * tile_stride, ld);
+        for (int c = 0; c < C && ok; ++c) ok = wait_counter(counter(a, i, k, c), task.v[0], a, spins, t);
         break;
       case UNMQR:
-        run_update<NB, K_UNM>(sm, tileptr(i, k), a.Tg + ((int64_t)i * a.nt + k) * tile_stride, nullptr,
-                              tileptr(i, j) + colchunk, ld);
+        ok = wait_counter(counter(a, i, k, 0), task.v[0], a, spins, t) &&
+             wait_counter(counter(a, i, j, ch), task.v[1], a, spins, t);
         break;
-      case TSMQR:
-        run_update<NB, K_TS>(sm, tileptr(i, k), a.Tk + ((int64_t)i * a.nt + k) * tile_stride,
-                             tileptr(piv, j) + colchunk, tileptr(i, j) + colchunk, ld);
+      case TSQRT:
+      case TTQRT:
+        for (int c = 0; c < C && ok; ++c)
+          ok = wait_counter(counter(a, piv, k, c), task.v[0], a, spins, t) &&
+               wait_counter(counter(a, i, k, c), task.v[1], a, spins, t);
         break;
       default:
-        run_update<NB, K_TT>(sm, tileptr(i, k), a.Tk + ((int64_t)i * a.nt + k) * tile_stride,
-                             tileptr(piv, j) + colchunk, tileptr(i, j) + colchunk, ld);
+        ok = wait_counter(counter(a, i, k, 0), task.v[0], a, spins, t) &&
+             wait_counter(counter(a, piv, j, ch), task.v[1], a, spins, t) &&
+             wait_counter(counter(a, i, j, ch), task.v[2], a, spins, t);
         break;
     }
-    // ---- release
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      auto bump = [&](int32_t* c) { __hip_atomic_fetch_add(c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-      switch (op) {
-        case GEQRT:
-          for (int c = 0; c < C; ++c) bump(ctr(i, k, c));
-          break;
-        case UNMQR:
-          bump(ctr(i, j, ch));
-          break;
-        case TSQRT:
-        case TTQRT:
-          for (int c = 0; c < C; ++c) {
-            bump(ctr(piv, k, c));
-            bump(ctr(i, k, c));
-          }
-          break;
-        default:
-          bump(ctr(piv, j, ch));
-          bump(ctr(i, j, ch));
-          break;
-      }
+    sm.ok = ok ? 1 : 0;
+    trace(a, t, ok ? TR_READY : TR_ABORT);
+  }
+  __syncthreads();
+  const int ok = __builtin_amdgcn_readfirstlane(sm.ok);
+  // the tiles written by the producers are visible from here on
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
+}
+
+// Publishes the task's tile writes and bumps the counters of the tiles it
+// wrote.
+template <int NB>
+__device__ __noinline__ void finish_task(const LaunchArgs& a, int t, const DevTask& task) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    trace(a, t, TR_DONE);
+    const int op = task.op, ch = task.chunk, i = task.row, piv = task.killer, k = task.k, j = task.j;
+    const int C = a.chunks;
+    auto bump = [&](int32_t* c) { __hip_atomic_fetch_add(c, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); };
+    switch (op) {
+      case GEQRT:
+        for (int c = 0; c < C; ++c) bump(counter(a, i, k, c));
+        break;
+      case UNMQR:
+        bump(counter(a, i, j, ch));
+        break;
+      case TSQRT:
+      case TTQRT:
+        for (int c = 0; c < C; ++c) {
+          bump(counter(a, piv, k, c));
+          bump(counter(a, i, k, c));
+        }
+        break;
+      default:
+        bump(counter(a, piv, j, ch));
+        bump(counter(a, i, j, ch));
+        break;
     }
+  }
+}
+
+__device__ __forceinline__ double* tile_ptr(const LaunchArgs& a, int nb, int r, int c) {
+  return a.A + (int64_t)r * nb + (int64_t)c * nb * a.lda;
+}
+
+__device__ __forceinline__ double* t_block(double* T, const LaunchArgs& a, int nb, int r, int c) {
+  return T + ((int64_t)r * a.nt + c) * nb * 16;
+}
+
+// One tile kernel per function (each gets its own register allocation).
+template <int NB, int KIND>
+__device__ __noinline__ void panel_task(const LaunchArgs& a, const DevTask& task) {
+  double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
+  run_panel<NB, KIND>(smem<NB>(), tile_ptr(a, NB, task.row, task.k),
+                      KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.k),
+                      t_block(T, a, NB, task.row, task.k), a.lda);
+}
+
+template <int NB, int KIND>
+__device__ __noinline__ void update_task(const LaunchArgs& a, const DevTask& task) {
+  double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
+  const int64_t colchunk = (int64_t)task.chunk * 64 * a.lda;
+  run_update<NB, KIND>(smem<NB>(), tile_ptr(a, NB, task.row, task.k), t_block(T, a, NB, task.row, task.k),
+                       KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.j) + colchunk,
+                       tile_ptr(a, NB, task.row, task.j) + colchunk, a.lda);
+}
+
+// Persistent scheduler.  Workgroups take task indices from a global cursor
+// in dispatch order (a topological order of the task graph), wait until the
+// dependency counters of the tiles the task touches reach the versions in
+// the task record, run it, and bump the counters of the tiles it wrote.
+// Every task a workgroup waits for was taken earlier by a running
+// workgroup, so the wait always ends.
+template <int NB>
+__global__ __launch_bounds__(NT, 2) void persistent_kernel(LaunchArgs a) {
+  for (;;) {
+    const int t = take_task<NB>(a);
+    if (t < 0) break;
+    const DevTask task = a.tasks[t];
+    if (!wait_task<NB>(a, t, task)) break;
+    switch (task.op) {
+      case GEQRT: panel_task<NB, K_UNM>(a, task); break;
+      case TSQRT: panel_task<NB, K_TS>(a, task); break;
+      case TTQRT: panel_task<NB, K_TT>(a, task); break;
+      case UNMQR: update_task<NB, K_UNM>(a, task); break;
+      case TSMQR: update_task<NB, K_TS>(a, task); break;
+      default: update_task<NB, K_TT>(a, task); break;
+    }
+    finish_task<NB>(a, t, task);
   }
 }
 
@@ -556,6 +649,17 @@ __global__ void zero2d_kernel(double* dst, int64_t ldd, int64_t m, int64_t n) {
   }
 }
 
+// Records the last HIP failure for hqr_last_error().
+static thread_local char g_last_error[256];
+
+int record_hip(hipError_t e, const char* where) {
+  if (e == hipSuccess) return 0;
+  snprintf(g_last_error, sizeof(g_last_error), "%s: %s", where, hipGetErrorString(e));
+  return HQR_ERR_HIP;
+}
+
+const char* last_error() { return g_last_error; }
+
 static int grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
@@ -566,19 +670,19 @@ static int grid_for(int64_t n) {
 int launch_zero_i32(int32_t* p, int64_t n, void* stream) {
   if (n <= 0) return 0;
   hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, p, n);
-  return hipGetLastError() == hipSuccess ? 0 : HQR_ERR_HIP;
+  return record_hip(hipGetLastError(), "zero_i32_kernel launch");
 }
 
 int launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t m, int64_t n, void* stream) {
   if (m <= 0 || n <= 0) return 0;
   hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(m * n)), dim3(256), 0, (hipStream_t)stream, src, lds, dst, ldd, m, n);
-  return hipGetLastError() == hipSuccess ? 0 : HQR_ERR_HIP;
+  return record_hip(hipGetLastError(), "copy2d_kernel launch");
 }
 
 int launch_zero2d(double* dst, int64_t ldd, int64_t m, int64_t n, void* stream) {
   if (m <= 0 || n <= 0) return 0;
   hipLaunchKernelGGL(zero2d_kernel, dim3(grid_for(m * n)), dim3(256), 0, (hipStream_t)stream, dst, ldd, m, n);
-  return hipGetLastError() == hipSuccess ? 0 : HQR_ERR_HIP;
+  return record_hip(hipGetLastError(), "zero2d_kernel launch");
 }
 
 template <int NB>
@@ -586,7 +690,8 @@ static int occupancy_workers() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_kernel<NB>, NT, 0) != hipSuccess || per < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_kernel<NB>, NT, sizeof(Smem<NB>)) != hipSuccess ||
+      per < 1)
     per = 1;
   return cus * per;
 }
@@ -603,12 +708,12 @@ int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream) {
   if (workers < 1) workers = 1;
   hipStream_t s = (hipStream_t)stream;
   switch (nb) {
-    case 64: hipLaunchKernelGGL(persistent_kernel<64>, dim3(workers), dim3(NT), 0, s, a); break;
-    case 128: hipLaunchKernelGGL(persistent_kernel<128>, dim3(workers), dim3(NT), 0, s, a); break;
-    case 256: hipLaunchKernelGGL(persistent_kernel<256>, dim3(workers), dim3(NT), 0, s, a); break;
+    case 64: hipLaunchKernelGGL(persistent_kernel<64>, dim3(workers), dim3(NT), sizeof(Smem<64>), s, a); break;
+    case 128: hipLaunchKernelGGL(persistent_kernel<128>, dim3(workers), dim3(NT), sizeof(Smem<128>), s, a); break;
+    case 256: hipLaunchKernelGGL(persistent_kernel<256>, dim3(workers), dim3(NT), sizeof(Smem<256>), s, a); break;
     default: return HQR_ERR_INTERNAL;
   }
-  return hipGetLastError() == hipSuccess ? 0 : HQR_ERR_HIP;
+  return record_hip(hipGetLastError(), "persistent_kernel launch");
 }
 
 }  // namespace hqr

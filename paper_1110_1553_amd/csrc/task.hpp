@@ -2,6 +2,8 @@
 // scheduler.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 #include "elim.hpp"
@@ -18,8 +20,13 @@ struct LaunchArgs {
   const DevTask* tasks;
   int64_t ntasks;
   int64_t spin_limit;
+  int32_t* trace;     // optional host-visible progress words, 2 per workgroup (null: off)
   int32_t mt, nt, chunks;
 };
+
+// Progress phases published per workgroup when tracing is on.
+enum TracePhase { TR_POPPED = 1, TR_READY = 2, TR_DONE = 3, TR_EXIT = 4, TR_ABORT = 5 };
+constexpr int kTraceSlots = 4096;  // workgroups traced
 
 // Zero `n` int32 words on `stream` with a fill kernel.
 int launch_zero_i32(int32_t* p, int64_t n, void* stream);
@@ -33,6 +40,11 @@ int launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int6
                   void* stream);
 // Zero an m x n column-major block.
 int launch_zero2d(double* dst, int64_t ldd, int64_t m, int64_t n, void* stream);
+
+// Stores "where: message" of a failed HIP call for hqr_last_error(); returns
+// HQR_ERR_HIP on failure, 0 on success.
+int record_hip(hipError_t e, const char* where);
+const char* last_error();
 
 // Workgroups that fit on the device at once (per CU occupancy x CUs).
 int default_workers(int nb);

@@ -37,7 +37,7 @@ def factor_on_gpu(A_np, params, exec_=None):
         exec_ = h.make_exec(spin_limit=SPIN)
     elif exec_.spin_limit == 0:
         exec_.spin_limit = SPIN
-    work = h.factor(dA, params, exec_)
+    work = h.factor(dA, params, exec_, timeout_s=60.0)
     torch.cuda.synchronize()
     return dA, work
 
