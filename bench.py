@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the tiled hierarchical Householder QR on one MI355X.
+
+A step is one factorization (hqr_factor: one persistent GPU launch running
+every tile kernel of the elimination list) of a synthetic matrix already
+resident in HBM.  The headline workload is the tall-skinny FP64 QR of a
+131072 x 2048 iid N(0,1) matrix with 256 x 256 tiles and the hierarchical
+tree (TS domains of 4 tiles, Greedy low level, domino coupling level,
+Fibonacci high level, 8 virtual clusters).  Throughput is reported in GFLOP/s
+of the Householder count 2MN^2 - 2N^3/3 (the total weight of any elimination
+list, Section II of the paper), next to the FP64 matrix peak of MI355X.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
+METRIC = "QR GFLOP/s & % FP64 MFMA peak; lstsq solves/sec + p50/p99 latency"
+
+HQR = dict(nb=256, p=8, a=4, low="greedy", high="fibonacci", coupling="chain", domino=1)
+WORKLOADS = {
+    "tall-hqr": dict(M=131072, N=2048, seed=2, gen="gaussian", params=HQR,
+                     label="tall-skinny FP64 QR 131072x2048 iid N(0,1), nb=256, hierarchical tree "
+                           "(TS domains a=4, Greedy low, domino coupling, Fibonacci high, p=8)"),
+    "tall-flat": dict(M=131072, N=2048, seed=2, gen="gaussian", params=dict(nb=256, p=1, a=512, low="flat"),
+                      label="tall-skinny FP64 QR 131072x2048, nb=256, FlatTree with TS kernels"),
+    "tall-binary": dict(M=131072, N=2048, seed=2, gen="gaussian", params=dict(nb=256, p=1, a=1, low="binary"),
+                        label="tall-skinny FP64 QR 131072x2048, nb=256, BinaryTree with TT kernels"),
+    "square-greedy": dict(M=16384, N=16384, seed=3, gen="graded", params=dict(nb=256, p=1, a=1, low="greedy"),
+                          label="square FP64 QR 16384^2, sigma logspaced 1..1e-8, nb=256, Greedy with TT kernels"),
+    "square-flat": dict(M=16384, N=16384, seed=3, gen="graded", params=dict(nb=256, p=1, a=64, low="flat"),
+                        label="square FP64 QR 16384^2, sigma logspaced 1..1e-8, nb=256, FlatTree with TS kernels"),
+}
+
+
+def qr_flops(M, N):
+    return 2.0 * M * N * N - 2.0 * N ** 3 / 3.0
+
+
+def make_input(w, device):
+    from paper_1110_1553_amd import inputs
+
+    if w["gen"] == "gaussian":
+        return inputs.gaussian_device(w["M"], w["N"], w["seed"], device)
+    return inputs.graded_device(w["M"], w["seed"], 1e-8, device)
+
+
+def run_workload(name, steps, warmup, device, keep_result=False):
+    import torch
+
+    import paper_1110_1553_amd as h
+
+    w = WORKLOADS[name]
+    M, N = w["M"], w["N"]
+    params = h.make_params(**w["params"])
+    pristine = h.colmajor(make_input(w, device))
+    work = h.Workspace(M, N, params, device=device)
+    stream = torch.cuda.current_stream(device)
+    # warm-up: builds and uploads the task plan, loads the code object
+    scratch = torch.empty_like(pristine)
+    for _ in range(warmup):
+        scratch.copy_(pristine)
+        h.factor(scratch, params, work=work, stream=stream)
+    del scratch
+    copies = [pristine.clone() for _ in range(steps)]
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize(device)
+    t0 = time.perf_counter()
+    for s in range(steps):
+        starts[s].record(stream)
+        h.factor(copies[s], params, work=work, stream=stream, check=False)
+        ends[s].record(stream)
+    torch.cuda.synchronize(device)
+    wall = time.perf_counter() - t0
+    status = h.status(work, stream)
+    if status != 0:
+        raise RuntimeError("device status %d in workload %s" % (status, name))
+    ev = [starts[s].elapsed_time(ends[s]) / 1e3 for s in range(steps)]
+    fl = qr_flops(M, N)
+    out = {
+        "workload": name,
+        "label": w["label"],
+        "M": M, "N": N,
+        "params": w["params"],
+        "wall_s": wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "gflops": fl * steps / wall / 1e9,
+        "launch_s": sum(ev) / len(ev),
+        "launch_s_min": min(ev),
+        "launch_s_max": max(ev),
+        "tflops_launch": fl / (sum(ev) / len(ev)) / 1e12,
+    }
+    out["frac_peak"] = out["tflops_launch"] / PEAK_FP64_TFLOPS
+    result = copies[0] if keep_result else None
+    host_sample = None
+    if keep_result:
+        host_sample = pristine[:, :1024].cpu().numpy()
+    del copies, pristine, work
+    torch.cuda.empty_cache()
+    return out, result, host_sample
+
+
+def cpu_baseline(sample):
+    """The oracle (unblocked Householder QR) on a bounded sample of the workload."""
+    import numpy as np
+
+    from oracle import qr as oq
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    A = np.asfortranarray(sample)
+    m, n = A.shape
+    t = time.perf_counter()
+    oq.factor(A, nthreads=threads)
+    dt = time.perf_counter() - t
+    return {"value": qr_flops(m, n) / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "oracle QR of the leading %dx%d block of the benchmark matrix (%.1f s)" % (m, n, dt)}, A
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="tall-hqr", choices=sorted(WORKLOADS))
+    ap.add_argument("--secondary", default="tall-flat,tall-binary,square-greedy,square-flat",
+                    help="comma-separated workloads also timed (1 step each after 1 warm-up); empty for none")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    device = torch.device("cuda:0")
+    torch.cuda.set_device(device)
+    primary, _, host_sample = run_workload(args.workload, args.steps, args.warmup, device, keep_result=True)
+    secondary = []
+    for name in [s for s in args.secondary.split(",") if s]:
+        if name == args.workload:
+            continue
+        res, _, _ = run_workload(name, 1, 1, device)
+        secondary.append({k: res[k] for k in ("workload", "label", "ms_per_step", "gflops", "tflops_launch",
+                                              "frac_peak")})
+    cpu = None
+    if not args.no_cpu_baseline and host_sample is not None:
+        cpu, _ = cpu_baseline(host_sample)
+    w = WORKLOADS[args.workload]
+    line = {
+        "metric": METRIC,
+        "value": round(primary["gflops"], 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(primary["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["label"], "M": w["M"], "N": w["N"], "tree": w["params"],
+                   "frac_fp64_peak": round(primary["frac_peak"], 4)},
+        "roofline": {"bound": "mfma", "achieved": round(primary["tflops_launch"], 3), "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(primary["frac_peak"], 4), "traffic": None,
+                     "kernel": "persistent_kernel<256> (all tile kernels of one factorization)",
+                     "launch_ms": round(1e3 * primary["launch_s"], 3)},
+        "cpu_baseline": cpu,
+        "secondary": secondary,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,37 +1,67 @@
 """Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
 
 This module only draws random matrices; it holds none of the factorization's
-arithmetic.  All matrices are float64 in column-major (Fortran) order.
+arithmetic.  All matrices are float64 and column-major: numpy arrays in
+Fortran order, torch tensors of shape (M, N) with strides (1, M).
 
-* :func:`gaussian` -- iid N(0,1) entries, ``numpy.random.default_rng(seed)``.
-* :func:`graded` -- U diag(sigma) V^T with sigma logspaced from 1 down to
-  ``smin`` and Haar-distributed orthogonal U, V (QR of a Gaussian with the
-  usual sign fix, by numpy's LAPACK binding); used for the ill-conditioned
-  square workload.
+* :func:`gaussian` / :func:`gaussian_device` -- iid N(0,1) entries
+  (numpy ``default_rng(seed)`` on the host; torch's seeded Philox generator
+  on the device for the large benchmark matrices).
+* :func:`graded` / :func:`graded_device` -- U diag(sigma) V^T with sigma
+  logspaced from 1 down to ``smin`` and random orthogonal U, V.  U and V are
+  exponentials of random skew-symmetric matrices (exp(K) with K = -K^T is
+  orthogonal), so no QR is involved in making the input.
 """
 import numpy as np
 
 
 def gaussian(M: int, N: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
-    # draw column by column so the first columns do not depend on N
+    # drawn column by column, so the leading columns do not depend on N
     return np.asfortranarray(rng.standard_normal((N, M)).T)
 
 
-def haar(n: int, rng) -> np.ndarray:
-    Z = rng.standard_normal((n, n))
-    Q, R = np.linalg.qr(Z)
-    return Q * np.where(np.diagonal(R) < 0, -1.0, 1.0)
+def gaussian_device(M: int, N: int, seed: int, device="cuda"):
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return torch.randn((N, M), generator=g, device=device, dtype=torch.float64).t()
 
 
-def graded(n: int, seed: int, smin: float = 1e-8, m: int = 0) -> np.ndarray:
-    """m x n (m defaults to n) matrix U diag(sigma) V^T, sigma_i = smin^(i/(n-1))."""
+def _skew(n: int, rng) -> np.ndarray:
+    S = rng.standard_normal((n, n)) * (1.5 / np.sqrt(2.0 * n))
+    return S - S.T
+
+
+def orthogonal(n: int, rng) -> np.ndarray:
+    import scipy.linalg
+
+    return scipy.linalg.expm(_skew(n, rng))
+
+
+def graded(n: int, seed: int, smin: float = 1e-8) -> np.ndarray:
+    """n x n matrix U diag(sigma) V^T, sigma_i = smin^(i/(n-1))."""
     rng = np.random.default_rng(seed)
-    m = m or n
     sigma = np.logspace(0.0, np.log10(smin), n)
-    if m == n:
-        U = haar(n, rng)
-    else:
-        U, _ = np.linalg.qr(rng.standard_normal((m, n)))
-    V = haar(n, rng)
+    U = orthogonal(n, rng)
+    V = orthogonal(n, rng)
     return np.asfortranarray((U * sigma) @ V.T)
+
+
+def graded_device(n: int, seed: int, smin: float = 1e-8, device="cuda"):
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def orth():
+        S = torch.randn((n, n), generator=g, device=device, dtype=torch.float64) * (1.5 / (2.0 * n) ** 0.5)
+        return torch.linalg.matrix_exp(S - S.t())
+
+    sigma = torch.logspace(0.0, float(np.log10(smin)), n, device=device, dtype=torch.float64)
+    U = orth()
+    V = orth()
+    # row-major V (U diag(sigma))^T is the column-major storage of U diag(sigma) V^T
+    At = V @ (U * sigma).t()
+    return At.t()
