@@ -214,6 +214,15 @@ const char* hqr_strerror(int code);
  * library (empty if none). */
 const char* hqr_last_error(void);
 
+/* Per-task timeline of the last launch in this process, recorded only when
+ * the environment variable HQR_TIMELINE=1 is set (profiling aid).  For task
+ * t of the dispatch order (see hqr_plan_tasks): out[4t] = clock when a
+ * workgroup picked it, out[4t+1] = when its inputs were ready, out[4t+2] =
+ * when it finished (100 MHz real-time clock ticks), out[4t+3] = workgroup
+ * index | XCD index << 16.  Synchronizes `stream`.  out may be NULL to count.
+ * Errors: -3 cap too small, -4 count is NULL. */
+int hqr_timeline(void* stream, uint64_t* out, int64_t cap, int64_t* count);
+
 /* Library version string. */
 const char* hqr_version(void);
 

@@ -41,7 +41,7 @@ TASK_DTYPE = np.dtype([("op", "u1"), ("chunk", "u1"), ("row", "<u2"), ("killer",
                        ("j", "<u2"), ("pad", "<u2"), ("v", "<u4", (3,))])
 
 EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size", "hqr_factor",
-           "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_version")
+           "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_timeline", "hqr_version")
 
 _lib = None
 
@@ -74,6 +74,8 @@ def load():
     lib.hqr_release_plans.restype = None
     lib.hqr_strerror.argtypes = [ctypes.c_int]
     lib.hqr_strerror.restype = ctypes.c_char_p
+    lib.hqr_timeline.argtypes = [vp, vp, i64, P(i64)]
+    lib.hqr_timeline.restype = ctypes.c_int
     lib.hqr_last_error.argtypes = []
     lib.hqr_last_error.restype = ctypes.c_char_p
     lib.hqr_version.argtypes = []
@@ -165,6 +167,18 @@ def status(dwork: int, stream: int, timeout_s: float = 0.0, detail: bool = False
     _check("hqr_status_ex", load().hqr_status_ex(ctypes.c_void_p(dwork), ctypes.c_void_p(stream), timeout_s,
                                                  ctypes.byref(s), d))
     return (s.value, list(d)) if detail else s.value
+
+
+def timeline(stream: int) -> np.ndarray:
+    """(ntasks, 4) uint64 timeline of the last launch (HQR_TIMELINE=1)."""
+    lib = load()
+    n = ctypes.c_int64()
+    _check("hqr_timeline", lib.hqr_timeline(ctypes.c_void_p(stream), None, 0, ctypes.byref(n)))
+    out = np.zeros((n.value, 4), dtype=np.uint64)
+    if n.value:
+        _check("hqr_timeline", lib.hqr_timeline(ctypes.c_void_p(stream), ctypes.c_void_p(out.ctypes.data), n.value,
+                                                ctypes.byref(n)))
+    return out
 
 
 def release_plans() -> None:

@@ -37,6 +37,28 @@ struct DevicePlan {
 std::mutex g_mu;
 int32_t* g_trace = nullptr;  // pinned host words written by the GPU when HQR_TRACE is set
 
+// Per-task timestamps of the last launch when HQR_TIMELINE is set.
+uint64_t* g_timeline = nullptr;
+int64_t g_timeline_cap = 0, g_timeline_n = 0;
+
+uint64_t* timeline_buffer(int64_t ntasks) {
+  static bool want = [] {
+    const char* e = getenv("HQR_TIMELINE");
+    return e && atoi(e) != 0;
+  }();
+  if (!want) return nullptr;
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (g_timeline_cap < ntasks) {
+    if (g_timeline) (void)hipFree(g_timeline);
+    g_timeline = nullptr;
+    g_timeline_cap = 0;
+    if (hipMalloc(&g_timeline, (size_t)ntasks * 4 * sizeof(uint64_t)) != hipSuccess) return nullptr;
+    g_timeline_cap = ntasks;
+  }
+  g_timeline_n = ntasks;
+  return g_timeline;
+}
+
 int32_t* trace_buffer() {
   static bool want = [] {
     const char* e = getenv("HQR_TRACE");
@@ -219,6 +241,7 @@ int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* 
   a.ntasks = (int64_t)dp->plan.dev.size();
   a.spin_limit = ex.spin_limit > 0 ? ex.spin_limit : kDefaultSpinLimit;
   a.trace = trace_buffer();
+  a.timeline = timeline_buffer(a.ntasks);
   if (a.trace) std::memset(a.trace, 0, 2 * kTraceSlots * sizeof(int32_t));
   a.mt = L.mt;
   a.nt = L.nt;
@@ -310,6 +333,16 @@ const char* hqr_strerror(int code) {
 }
 
 const char* hqr_last_error(void) { return last_error(); }
+
+int hqr_timeline(void* stream, uint64_t* out, int64_t cap, int64_t* count) {
+  if (!count) return -4;
+  *count = g_timeline ? g_timeline_n : 0;
+  if (!out || !g_timeline) return 0;
+  if (cap < g_timeline_n) return -3;
+  if (int rc = record_hip(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize")) return rc;
+  return record_hip(hipMemcpy(out, g_timeline, (size_t)g_timeline_n * 4 * sizeof(uint64_t), hipMemcpyDeviceToHost),
+                    "hipMemcpy(timeline)");
+}
 
 const char* hqr_version(void) { return "hqr-mi355x 0.1"; }
 

@@ -291,81 +291,92 @@ __device__ __forceinline__ void run_update(Smem<NB>& sm, const double* V, const 
 // With alpha = head and s = ||tail||: s = 0 gives tau = 0 (H = I);
 // otherwise beta = -sign(alpha) sqrt(alpha^2 + s^2), tau = (beta - alpha)/beta,
 // tail /= (alpha - beta), head = beta.
+//
+// The 16 columns of a panel stay in registers during the column loop:
+// thread (cc, q) = (tid / 16, tid % 16) holds column c0 + cc at the rows
+// base + q + 16 m (base = c0 for GEQRT, 0 otherwise), so the reductions over
+// rows are 16-lane shuffles inside one wavefront.  The only data crossing
+// groups is the reflector being applied, published through LDS (double
+// buffered), which costs one workgroup barrier per column.
 template <int NB, int KIND>
 __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, double* T, int64_t ld) {
   constexpr int NP = NB / IB;
+  constexpr int NM = NB / 16;  // rows per thread
   const int tid = threadIdx.x;
   const Lane L;
-  const int cc = tid >> 4;   // column of the panel this thread updates
-  const int rq = tid & 15;   // it handles rows r with r % 16 == rq
+  const int cc = tid >> 4;   // panel column of this thread
+  const int q = tid & 15;    // its rows are base + q + 16 m
   double* Vs = sm.V[0];
   double* Ts = sm.T[0];
-  double* Rs = sm.R;
-  double* Zs = sm.V[1];  // Gram entries v_i^T v_j of the panel (the second V buffer is free here)
+  double* Zs = sm.R;         // Gram entries v_i^T v_j of the panel
+  double* Vb = sm.V[1];      // published reflector, two buffers of NB
   for (int p = 0; p < NP; ++p) {
     const int c0 = 16 * p;
-    // ---- load the panel (masked) and, for TS/TT, the diagonal block of R
-    const int rlo = (KIND == K_UNM) ? c0 : 0;
-    const int rhi = (KIND == K_TT) ? c0 + 16 : NB;
-    for (int e = tid; e < NB * 16; e += NT) {
-      const int col = e / NB, row = e % NB;
-      if (row >= rlo && row < rhi) {
-        double x = A[row + (int64_t)(c0 + col) * ld];
-        if (KIND == K_TT && row > c0 + col) x = 0.0;  // the stored GEQRT reflectors, not R
-        Vs[row * LDV + col] = x;
-      }
+    const int base = (KIND == K_UNM) ? c0 : 0;
+    // ---- the panel into registers (inactive rows: zero, never stored)
+    double x[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int r = base + q + 16 * m;
+      bool act = r < NB;
+      if (KIND == K_TT) act = r <= c0 + cc;  // below: the tile's stored GEQRT reflectors
+      x[m] = act ? A[r + (int64_t)(c0 + cc) * ld] : 0.0;
     }
-    if (KIND != K_UNM) {
-      const int a = tid & 15, b = tid >> 4;
-      const double x = R[(c0 + a) + (int64_t)(c0 + b) * ld];
-      Rs[a * LDV + b] = (a <= b) ? x : 0.0;
-    }
-    __syncthreads();
-    // ---- unblocked factorization of the panel
+    double rv = 0.0;  // TS/TT: R(c0 + q, c0 + cc) of the killer's diagonal block
+    if (KIND != K_UNM && q <= cc) rv = R[(c0 + q) + (int64_t)(c0 + cc) * ld];
+    // ---- unblocked factorization, one reflector per column
     for (int jj = 0; jj < 16; ++jj) {
-      // The owners of column jj read entries that other lanes of their 16-lane
-      // group wrote in the previous step; the group is one wavefront slice, so
-      // program order inside the wave is the only ordering needed.
-      __builtin_amdgcn_wave_barrier();
       const int j = c0 + jj;
-      const int tlo = (KIND == K_UNM) ? j + 1 : 0;
-      const int thi = (KIND == K_TT) ? j + 1 : NB;
-      double* headp = (KIND == K_UNM) ? &Vs[j * LDV] : &Rs[jj * LDV];  // head row
+      double* vb = Vb + (jj & 1) * NB;
       if (cc == jj) {
-        const double alpha = headp[jj];  // read by every lane before the owner rewrites it
+        const double alpha = (KIND == K_UNM) ? __shfl(x[0], jj, 16) : __shfl(rv, jj, 16);
         double ss = 0.0;
-        for (int r = rq; r < NB; r += 16)
-          if (r >= tlo && r < thi) ss += Vs[r * LDV + jj] * Vs[r * LDV + jj];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+          const int r = base + q + 16 * m;
+          const bool tail = (KIND == K_UNM) ? (r > j && r < NB) : (KIND == K_TT ? r <= j : true);
+          if (tail) ss += x[m] * x[m];
+        }
         ss = sum16(ss);
-        double tau = 0.0;
+        double tau = 0.0, beta = alpha, scale = 1.0;
         if (ss != 0.0) {
-          double beta = sqrt(alpha * alpha + ss);
+          beta = sqrt(alpha * alpha + ss);
           if (alpha >= 0.0) beta = -beta;
           tau = (beta - alpha) / beta;
-          const double scale = 1.0 / (alpha - beta);
-          for (int r = rq; r < NB; r += 16)
-            if (r >= tlo && r < thi) Vs[r * LDV + jj] *= scale;
-          if (rq == ((KIND == K_UNM) ? (j & 15) : 0)) headp[jj] = beta;
+          scale = 1.0 / (alpha - beta);
         }
-        if (rq == 0) sm.tau[jj] = tau;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+          const int r = base + q + 16 * m;
+          const bool tail = (KIND == K_UNM) ? (r > j && r < NB) : (KIND == K_TT ? r <= j : true);
+          const bool head = (KIND == K_UNM) && r == j;
+          if (tail) x[m] *= scale;
+          if (head) x[m] = beta;
+          if (base + q + 16 * m < NB) vb[q + 16 * m] = tail ? x[m] : (head ? 1.0 : 0.0);
+        }
+        if (KIND != K_UNM && q == jj) rv = beta;
+        if (q == 0) sm.tau[jj] = tau;
       }
       __syncthreads();
       if (cc != jj) {
         const double tau = sm.tau[jj];
-        // head-row term of v_jj^T column cc, read before the owner lane updates it
-        const double h = (KIND == K_UNM) ? Vs[j * LDV + cc] : (cc > jj ? headp[cc] : 0.0);
+        double v[NM];
         double d = 0.0;
-        for (int r = rq; r < NB; r += 16)
-          if (r >= tlo && r < thi) d += Vs[r * LDV + cc] * Vs[r * LDV + jj];
-        d = sum16(d) + h;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+          v[m] = (base + q + 16 * m < NB) ? vb[q + 16 * m] : 0.0;
+          d += v[m] * x[m];
+        }
+        d = sum16(d);
+        if (KIND != K_UNM && cc > jj) d += __shfl(rv, jj, 16);  // R(j, c0+cc) meets the unit entry of v
         if (cc > jj) {
           if (tau != 0.0) {
             const double f = tau * d;
-            for (int r = rq; r < NB; r += 16)
-              if (r >= tlo && r < thi) Vs[r * LDV + cc] -= Vs[r * LDV + jj] * f;
-            if (rq == ((KIND == K_UNM) ? (j & 15) : 0)) headp[cc] -= f;
+#pragma unroll
+            for (int m = 0; m < NM; ++m) x[m] -= f * v[m];
+            if (KIND != K_UNM && q == jj) rv -= f;
           }
-        } else if (rq == 0) {
+        } else if (q == 0) {
           Zs[cc * LDV + jj] = d;  // v_cc^T v_jj, consumed when T is formed
         }
       }
@@ -379,10 +390,13 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
         const double tj = sm.tau[jj];
+        double zc[16];
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) zc[qq] = (qq < jj) ? Zs[qq * LDV + jj] : 0.0;
         double s = 0.0;
 #pragma unroll
         for (int qq = 0; qq < 16; ++qq)
-          if (qq < jj && qq >= i) s += trow[qq] * Zs[qq * LDV + jj];
+          if (qq < jj && qq >= i) s += trow[qq] * zc[qq];
         trow[jj] = (i < jj) ? -tj * s : (i == jj ? tj : 0.0);
       }
 #pragma unroll
@@ -391,23 +405,22 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
         T[p * 256 + i + 16 * jj] = trow[jj];
       }
     }
-    // ---- write the factored panel back
-    for (int e = tid; e < NB * 16; e += NT) {
-      const int col = e / NB, row = e % NB;
-      bool w = row >= rlo && row < rhi;
-      if (KIND == K_TT) w = w && row <= c0 + col;
-      if (w) A[row + (int64_t)(c0 + col) * ld] = Vs[row * LDV + col];
+    // ---- the factored panel back to the tiles, and the V of the block update into LDS
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int r = base + q + 16 * m;
+      bool act = r < NB;
+      if (KIND == K_TT) act = r <= c0 + cc;
+      if (act) {
+        A[r + (int64_t)(c0 + cc) * ld] = x[m];
+        double vv = x[m];
+        if (KIND == K_UNM && r <= c0 + cc) vv = (r == c0 + cc) ? 1.0 : 0.0;  // unit diagonal, R above
+        Vs[r * LDV + cc] = vv;
+      } else if (KIND == K_TT && r < c0 + 16) {
+        Vs[r * LDV + cc] = 0.0;
+      }
     }
-    if (KIND != K_UNM) {
-      const int a = tid & 15, b = tid >> 4;
-      if (a <= b) R[(c0 + a) + (int64_t)(c0 + b) * ld] = Rs[a * LDV + b];
-    }
-    __syncthreads();
-    // ---- turn the staged panel into the V used by the block update
-    if (KIND == K_UNM) {
-      const int a = tid & 15, b = tid >> 4;
-      if (a <= b) Vs[(c0 + a) * LDV + b] = (a == b) ? 1.0 : 0.0;
-    }
+    if (KIND != K_UNM && q <= cc) R[(c0 + q) + (int64_t)(c0 + cc) * ld] = rv;
     __syncthreads();
     // ---- apply the panel's block reflector to the remaining columns
     for (int s = p + 1 + L.wave; s < NP; s += 4) {
@@ -422,12 +435,7 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
 }
 
 // ---------------------------------------------------------------------------
-// Persistent scheduler.  Workgroups take task indices from a global cursor
-// in dispatch order (a topological order of the task graph), wait until the
-// dependency counters of the tiles the task touches reach the versions in
-// the task record, run it, and bump the counters of the tiles it wrote.
-// Every task a workgroup waits for was taken earlier by a running
-// workgroup, so the wait always ends.
+// Scheduler steps.
 
 // Waits until *c >= v.  Returns false when the launch has been aborted: by
 // this wait running past the spin limit (it then records the abort and what
@@ -459,6 +467,22 @@ __device__ __forceinline__ void trace(const LaunchArgs& a, int t, int phase) {
   if (a.trace && blockIdx.x < kTraceSlots) {
     __hip_atomic_store(&a.trace[2 * blockIdx.x], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(&a.trace[2 * blockIdx.x + 1], phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// Index of the XCD (accelerator complex die) running the wave.
+__device__ __forceinline__ int xcc_id() {
+  int x = 0;
+  __asm__ __volatile__("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+  return x & 0xf;
+}
+
+// Timeline record of task t: [0] picked, [1] inputs ready, [2] done (100 MHz
+// real-time clock), [3] workgroup | XCD << 16.
+__device__ __forceinline__ void stamp(const LaunchArgs& a, int t, int slot) {
+  if (a.timeline && t >= 0) {
+    a.timeline[4 * (int64_t)t + slot] = __builtin_amdgcn_s_memrealtime();
+    if (slot == 0) a.timeline[4 * (int64_t)t + 3] = (uint64_t)blockIdx.x | ((uint64_t)xcc_id() << 16);
   }
 }
 
@@ -496,6 +520,7 @@ __device__ __noinline__ int take_task(const LaunchArgs& a) {
     if (t >= a.ntasks) t = -1;
     sm.task = t;
     trace(a, t, t < 0 ? TR_EXIT : TR_POPPED);
+    stamp(a, t, 0);
   }
   __syncthreads();
   return __builtin_amdgcn_readfirstlane(sm.task);
@@ -533,6 +558,7 @@ __device__ __noinline__ int wait_task(const LaunchArgs& a, int t, const DevTask&
     }
     sm.ok = ok ? 1 : 0;
     trace(a, t, ok ? TR_READY : TR_ABORT);
+    stamp(a, t, 1);
   }
   __syncthreads();
   const int ok = __builtin_amdgcn_readfirstlane(sm.ok);
@@ -549,6 +575,7 @@ __device__ __noinline__ void finish_task(const LaunchArgs& a, int t, const DevTa
   __syncthreads();
   if (threadIdx.x == 0) {
     trace(a, t, TR_DONE);
+    stamp(a, t, 2);
     const int op = task.op, ch = task.chunk, i = task.row, piv = task.killer, k = task.k, j = task.j;
     const int C = a.chunks;
     auto bump = [&](int32_t* c) { __hip_atomic_fetch_add(c, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); };

@@ -21,6 +21,7 @@ struct LaunchArgs {
   int64_t ntasks;
   int64_t spin_limit;
   int32_t* trace;     // optional host-visible progress words, 2 per workgroup (null: off)
+  uint64_t* timeline; // optional per-task timestamps, 4 words per task (null: off)
   int32_t mt, nt, chunks;
 };
 
