@@ -170,7 +170,8 @@ int hqr_plan_tasks(int32_t mt, int32_t nt, const hqr_params* params, int32_t ord
 
 /* Bytes of device workspace hqr_factor needs for an M x N matrix: the T
  * factors of every tile kernel, the per-tile dependency counters, a status
- * word and, when M or N is not a multiple of nb, a zero-padded copy of A. */
+ * word and a tile-contiguous copy of A (each nb x nb tile stored
+ * contiguously, zero-padded beyond M and N) that the kernels work on. */
 int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* bytes);
 
 /* QR factorization A = Q R (Section II; the result is the Householder QR of
@@ -180,11 +181,15 @@ int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* b
  *           elsewhere.  Q is never formed.
  *   M >= N >= 1.
  *   dwork   device workspace of at least hqr_workspace_size bytes; it holds
- *           the T factors, so keep it unchanged while the factorization is
- *           used (hqr_apply_qt).
+ *           the T factors and the factored tiles, so keep it unchanged while
+ *           the factorization is used (hqr_apply_qt).  Any alignment of dA
+ *           and any lda >= M are accepted: the kernels work on the workspace's
+ *           tile-contiguous copy, filled from dA before the launch and copied
+ *           back after it, on `stream`.
  *   exec    NULL for defaults.
- * Errors: -2 if M < N or M < 1, -3 if N < 1, -4 if lda < M, -5 bad params,
- * -7 workspace too small.  Runtime failures inside the launch (watchdog) are
+ * Errors: -1 if dA is NULL, -2 if M < N or M < 1 (or more than 65535 tile
+ * rows), -3 if N < 1, -4 if lda < M, -5 bad params, -6 bad exec.order,
+ * -7 if dwork is NULL, -8 workspace too small.  Runtime failures inside the launch (watchdog) are
  * reported by hqr_status.  The first call for a given (tile grid, params,
  * exec.order) builds the task plan on the host and uploads it to device
  * memory owned by the library (kept until hqr_release_plans). */

@@ -81,26 +81,24 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
   int32_t mt, nt, chunks;
-  size_t ctrl, cnt, tg, tk, pad, total;
-  bool padded;
-  int64_t ldp;
+  size_t ctrl, cnt, tg, tk, tiles, total;
 };
 
+// Workspace: control words, dependency counters, the T factors of the panel
+// kernels (one nb x 16 block column per tile and kind) and the
+// tile-contiguous copy of the matrix the factorization works on.
 Layout layout_for(int64_t M, int64_t N, const hqr_params& p) {
   Layout L{};
   L.mt = (int32_t)((M + p.nb - 1) / p.nb);
   L.nt = (int32_t)((N + p.nb - 1) / p.nb);
   L.chunks = chunks_for(p.nb);
-  L.padded = (M % p.nb) != 0 || (N % p.nb) != 0;
-  L.ldp = (int64_t)L.mt * p.nb;
   const size_t tiles = (size_t)L.mt * L.nt;
   size_t off = 0;
   L.ctrl = off; off = align256(off + kCtrlWords * sizeof(int32_t));
   L.cnt = off; off = align256(off + tiles * L.chunks * sizeof(int32_t));
   L.tg = off; off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
   L.tk = off; off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
-  L.pad = off;
-  if (L.padded) off = align256(off + (size_t)L.ldp * L.nt * p.nb * sizeof(double));
+  L.tiles = off; off = align256(off + tiles * (size_t)p.nb * p.nb * sizeof(double));
   L.total = off;
   return L;
 }
@@ -220,10 +218,6 @@ int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* 
   const Layout L = layout_for(M, N, p);
   if (L.mt > 65535 || L.nt > 65535) return -2;
   if (work_bytes < L.total) return -8;
-  if (!L.padded && ((lda & 1) || ((uintptr_t)dA & 15))) {
-    // the tile kernels move two doubles per access; the padded path handles ragged shapes only
-    return (lda & 1) ? -4 : -1;
-  }
   hqr_exec ex{0, 0, 0};
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -6;
@@ -246,20 +240,14 @@ int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* 
   a.mt = L.mt;
   a.nt = L.nt;
   a.chunks = L.chunks;
-  if (L.padded) {
-    a.A = (double*)(w + L.pad);
-    a.lda = L.ldp;
-    if ((rc = launch_zero2d(a.A, a.lda, a.lda, (int64_t)L.nt * p.nb, stream))) return rc;
-    if ((rc = launch_copy2d(dA, lda, a.A, a.lda, M, N, stream))) return rc;
-  } else {
-    a.A = dA;
-    a.lda = lda;
-  }
+  a.A = (double*)(w + L.tiles);
+  a.lda = p.nb;
+  if ((rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, L.mt, L.nt, true, stream))) return rc;
   const int64_t nwords = (int64_t)((L.tg - L.ctrl) / sizeof(int32_t));  // ctrl + counters
   if ((rc = launch_zero_i32(a.ctrl, nwords, stream))) return rc;
   int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb);
   if ((rc = launch_persistent(p.nb, a, workers, stream))) return rc;
-  if (L.padded && (rc = launch_copy2d(a.A, a.lda, dA, lda, M, N, stream))) return rc;
+  if ((rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, L.mt, L.nt, false, stream))) return rc;
   return 0;
 }
 

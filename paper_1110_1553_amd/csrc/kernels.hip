@@ -59,11 +59,24 @@ __device__ __forceinline__ void st4(double* p, d4 v) {
   *reinterpret_cast<d2*>(p + 2) = y;
 }
 
+// One DPP step on a double: each lane receives the value of the lane picked
+// by `ctrl` inside its row of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 16 lanes of a DPP row, returned in every lane of the row.
+// Each step adds two partial sums in an order that does not depend on the
+// lane (addition is commutative), so all 16 lanes hold bitwise the same sum.
 __device__ __forceinline__ double sum16(double v) {
-  v += __shfl_xor(v, 1, 16);
-  v += __shfl_xor(v, 2, 16);
-  v += __shfl_xor(v, 4, 16);
-  v += __shfl_xor(v, 8, 16);
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x124>(v);  // row_ror:4
+  v += dpp<0x128>(v);  // row_ror:8
   return v;
 }
 
@@ -324,6 +337,7 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
     }
     double rv = 0.0;  // TS/TT: R(c0 + q, c0 + cc) of the killer's diagonal block
     if (KIND != K_UNM && q <= cc) rv = R[(c0 + q) + (int64_t)(c0 + cc) * ld];
+    Zs[cc * LDV + q] = 0.0;  // entries (i, j) with i >= j stay zero
     // ---- unblocked factorization, one reflector per column
     for (int jj = 0; jj < 16; ++jj) {
       const int j = c0 + jj;
@@ -388,15 +402,16 @@ __device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, do
       const int i = tid;
       double trow[16];
 #pragma unroll
+      for (int jj = 0; jj < 16; ++jj) trow[jj] = 0.0;
+#pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
         const double tj = sm.tau[jj];
         double zc[16];
 #pragma unroll
-        for (int qq = 0; qq < 16; ++qq) zc[qq] = (qq < jj) ? Zs[qq * LDV + jj] : 0.0;
+        for (int qq = 0; qq < 16; ++qq) zc[qq] = Zs[qq * LDV + jj];  // zero for qq >= jj
         double s = 0.0;
 #pragma unroll
-        for (int qq = 0; qq < 16; ++qq)
-          if (qq < jj && qq >= i) s += trow[qq] * zc[qq];
+        for (int qq = 0; qq < 16; ++qq) s += ((qq < jj && qq >= i) ? trow[qq] : 0.0) * zc[qq];
         trow[jj] = (i < jj) ? -tj * s : (i == jj ? tj : 0.0);
       }
 #pragma unroll
@@ -601,8 +616,10 @@ __device__ __noinline__ void finish_task(const LaunchArgs& a, int t, const DevTa
   }
 }
 
+// Tiles are stored contiguously (tile (r, c) at index c * mt + r, each one
+// column-major with leading dimension nb), so a tile spans a few pages only.
 __device__ __forceinline__ double* tile_ptr(const LaunchArgs& a, int nb, int r, int c) {
-  return a.A + (int64_t)r * nb + (int64_t)c * nb * a.lda;
+  return a.A + ((int64_t)c * a.mt + r) * nb * nb;
 }
 
 __device__ __forceinline__ double* t_block(double* T, const LaunchArgs& a, int nb, int r, int c) {
@@ -660,19 +677,22 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
     p[x] = 0;
 }
 
-__global__ void copy2d_kernel(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t m, int64_t n) {
-  const int64_t total = m * n;
+// Column-major M x N matrix (leading dimension lda) <-> tiles of nb x nb
+// (tile (i, j) at index j * mt + i, column-major inside).  `in` fills the
+// tiles and zeroes the padding beyond M and N; `out` copies the M x N part
+// back.  One thread per element of the padded matrix, rows fastest.
+__global__ void tile_copy_kernel(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int mt, int nt,
+                                 int in) {
+  const int64_t Mp = (int64_t)mt * nb, total = Mp * (int64_t)nt * nb;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = x % m, c = x / m;
-    dst[r + c * ldd] = src[r + c * lds];
-  }
-}
-
-__global__ void zero2d_kernel(double* dst, int64_t ldd, int64_t m, int64_t n) {
-  const int64_t total = m * n;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = x % m, c = x / m;
-    dst[r + c * ldd] = 0.0;
+    const int64_t r = x % Mp, c = x / Mp;
+    const int64_t i = r / nb, j = c / nb;
+    double* t = At + ((j * mt + i) * nb + (c - j * nb)) * nb + (r - i * nb);
+    const bool inside = r < M && c < N;
+    if (in)
+      *t = inside ? A[r + c * lda] : 0.0;
+    else if (inside)
+      A[r + c * lda] = *t;
   }
 }
 
@@ -689,7 +709,7 @@ const char* last_error() { return g_last_error; }
 
 static int grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
-  if (g > 4096) g = 4096;
+  if (g > 65536) g = 65536;
   if (g < 1) g = 1;
   return (int)g;
 }
@@ -700,16 +720,12 @@ int launch_zero_i32(int32_t* p, int64_t n, void* stream) {
   return record_hip(hipGetLastError(), "zero_i32_kernel launch");
 }
 
-int launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t m, int64_t n, void* stream) {
-  if (m <= 0 || n <= 0) return 0;
-  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(m * n)), dim3(256), 0, (hipStream_t)stream, src, lds, dst, ldd, m, n);
-  return record_hip(hipGetLastError(), "copy2d_kernel launch");
-}
-
-int launch_zero2d(double* dst, int64_t ldd, int64_t m, int64_t n, void* stream) {
-  if (m <= 0 || n <= 0) return 0;
-  hipLaunchKernelGGL(zero2d_kernel, dim3(grid_for(m * n)), dim3(256), 0, (hipStream_t)stream, dst, ldd, m, n);
-  return record_hip(hipGetLastError(), "zero2d_kernel launch");
+int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int mt, int nt, bool in,
+                     void* stream) {
+  const int64_t total = (int64_t)mt * nb * (int64_t)nt * nb;
+  hipLaunchKernelGGL(tile_copy_kernel, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, A, lda, At, M, N, nb,
+                     mt, nt, in ? 1 : 0);
+  return record_hip(hipGetLastError(), "tile_copy_kernel launch");
 }
 
 template <int NB>

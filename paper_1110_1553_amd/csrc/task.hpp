@@ -11,8 +11,8 @@
 namespace hqr {
 
 struct LaunchArgs {
-  double* A;          // tiled matrix, column-major, lda even, 16-byte aligned
-  int64_t lda;
+  double* A;          // tile-contiguous matrix: tile (r, c) at (c * mt + r) * nb * nb
+  int64_t lda;        // leading dimension inside a tile (= nb)
   double* Tg;         // T factors of GEQRT, one block column of nb x 16 per tile
   double* Tk;         // T factors of TSQRT/TTQRT, same layout
   int32_t* cnt;       // dependency counters, mt * nt * chunks
@@ -36,11 +36,11 @@ int launch_zero_i32(int32_t* p, int64_t n, void* stream);
 // workgroups.  nb is 64, 128 or 256.
 int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream);
 
-// Copy an m x n column-major block (device to device).
-int launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t m, int64_t n,
-                  void* stream);
-// Zero an m x n column-major block.
-int launch_zero2d(double* dst, int64_t ldd, int64_t m, int64_t n, void* stream);
+// Copies the column-major M x N matrix A (leading dimension lda) into the
+// tile-contiguous buffer At (mt x nt tiles of nb x nb, zero padding beyond M
+// and N) when `in`, or the M x N part of At back into A otherwise.
+int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int mt, int nt, bool in,
+                     void* stream);
 
 // Stores "where: message" of a failed HIP call for hqr_last_error(); returns
 // HQR_ERR_HIP on failure, 0 on success.

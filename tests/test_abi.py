@@ -54,10 +54,13 @@ def test_argument_checks_do_not_touch_the_device(hqr_lib):
     assert _lib.load().hqr_strerror(2).decode().startswith("a task waited")
 
 
-def test_workspace_grows_for_ragged_shapes(hqr_lib):
+def test_workspace_holds_padded_tile_copy(hqr_lib):
     import paper_1110_1553_amd as h
 
     p = h.make_params(nb=64)
     aligned = h.workspace_size(512, 256, p)
     ragged = h.workspace_size(500, 250, p)
-    assert ragged >= aligned + 512 * 256 * 8
+    # same 8 x 4 tile grid; the workspace holds the zero-padded tiles
+    assert ragged == aligned
+    assert aligned >= 512 * 256 * 8 + 2 * 8 * 4 * 64 * 16 * 8
+    assert h.workspace_size(513, 256, p) >= aligned + 4 * 64 * 64 * 8
