@@ -23,6 +23,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
+
+# HBM bytes per launch of persistent_kernel<256> from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE), each scaled by what the counter reads for the
+# copy-in kernel of known size.  Valid only for the kernel source they were
+# measured on (first 16 hex digits of the SHA-256 of csrc/kernels.hip).
+TRAFFIC = {
+    "tall-hqr": {"kernels_sha256": "82e32e2759dacd1a", "read": 64.54e9, "write": 41.83e9,
+                 "profile": "profiles/persistent_kernel_tall-hqr.md"},
+}
+
+
+def kernels_sha():
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_1110_1553_amd", "csrc", "kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(name):
+    t = TRAFFIC.get(name)
+    if t is None or t["kernels_sha256"] != kernels_sha():
+        return None
+    return t["read"] + t["write"]
 METRIC = "QR GFLOP/s & % FP64 MFMA peak; lstsq solves/sec + p50/p99 latency"
 
 HQR = dict(nb=256, p=8, a=4, low="greedy", high="fibonacci", coupling="chain", domino=1)
@@ -103,7 +127,7 @@ def run_workload(name, steps, warmup, device, keep_result=False):
     result = copies[0] if keep_result else None
     host_sample = None
     if keep_result:
-        host_sample = pristine[:, :1024].cpu().numpy()
+        host_sample = pristine.cpu().numpy()
     del copies, pristine, work
     torch.cuda.empty_cache()
     return out, result, host_sample
@@ -122,7 +146,7 @@ def cpu_baseline(sample):
     oq.factor(A, nthreads=threads)
     dt = time.perf_counter() - t
     return {"value": qr_flops(m, n) / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": "oracle QR of the leading %dx%d block of the benchmark matrix (%.1f s)" % (m, n, dt)}, A
+            "sample": "oracle QR of the whole %dx%d benchmark matrix, copied to the host (%.1f s)" % (m, n, dt)}, A
 
 
 def main():
@@ -143,16 +167,19 @@ def main():
     device = torch.device("cuda:0")
     torch.cuda.set_device(device)
     primary, _, host_sample = run_workload(args.workload, args.steps, args.warmup, device, keep_result=True)
+    print("bench: %s %.3f ms/step" % (args.workload, primary["ms_per_step"]), file=sys.stderr, flush=True)
     secondary = []
     for name in [s for s in args.secondary.split(",") if s]:
         if name == args.workload:
             continue
         res, _, _ = run_workload(name, 1, 1, device)
+        print("bench: %s %.3f ms/step" % (name, res["ms_per_step"]), file=sys.stderr, flush=True)
         secondary.append({k: res[k] for k in ("workload", "label", "ms_per_step", "gflops", "tflops_launch",
                                               "frac_peak")})
     cpu = None
     if not args.no_cpu_baseline and host_sample is not None:
         cpu, _ = cpu_baseline(host_sample)
+        print("bench: cpu baseline %s" % cpu["sample"], file=sys.stderr, flush=True)
     w = WORKLOADS[args.workload]
     line = {
         "metric": METRIC,
@@ -170,7 +197,8 @@ def main():
         "config": {"workload": w["label"], "M": w["M"], "N": w["N"], "tree": w["params"],
                    "frac_fp64_peak": round(primary["frac_peak"], 4)},
         "roofline": {"bound": "mfma", "achieved": round(primary["tflops_launch"], 3), "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(primary["frac_peak"], 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(primary["frac_peak"], 4),
+                     "traffic": traffic_for(args.workload), "traffic_unit": "bytes per launch (HBM read + write)",
                      "kernel": "persistent_kernel<256> (all tile kernels of one factorization)",
                      "launch_ms": round(1e3 * primary["launch_s"], 3)},
         "cpu_baseline": cpu,
