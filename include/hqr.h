@@ -58,7 +58,8 @@ enum {
   HQR_ERR_NOMEM = 4,      /* host or device allocation for the task plan failed */
   HQR_ERR_INTERNAL = 5,   /* internal inconsistency (bug) */
   HQR_ERR_INVALID_LIST = 6, /* an elimination list breaks the rules of Section II */
-  HQR_ERR_TIMEOUT = 7       /* hqr_status_ex: the stream did not finish in time */
+  HQR_ERR_TIMEOUT = 7,      /* hqr_status_ex: the stream did not finish in time */
+  HQR_ERR_SINGULAR = 8      /* hqr_lstsq: R has a zero diagonal entry (reported by hqr_status) */
 };
 
 /* Parameters of the hierarchical algorithm (Section IV-A and V-A).
@@ -196,9 +197,55 @@ int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* b
 int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params,
                const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
 
-/* Status word of the last factorization run in `dwork`: waits for the
- * stream (at most 300 s), then reports 0 or HQR_ERR_WATCHDOG in *status.
- * Returns HQR_ERR_TIMEOUT if the stream is still busy after the wait. */
+/* Bytes of the second workspace that hqr_apply_qt, hqr_apply_q and
+ * hqr_lstsq need for a right-hand side B of M rows and nrhs columns: a
+ * status word, one dependency counter per block and B in blocks of nb rows x
+ * 64 columns (zero-padded).  Errors: -1 M < 1, -2 nrhs < 1, -3 bad params. */
+int hqr_apply_workspace_size(int64_t M, int32_t nrhs, const hqr_params* params, size_t* bytes);
+
+/* B <- Q^T B with the Q of a finished hqr_factor (Section I: the update
+ * kernels UNMQR/TSMQR/TTMQR of Algorithm 2 replayed on B in the order of the
+ * elimination list).
+ *   M, N, params  exactly those given to hqr_factor.
+ *   dwork         the factorization's workspace (read only: V tiles, T).
+ *   dB            device, M x nrhs, column-major, ldb >= M; overwritten.
+ *   bwork         device workspace of hqr_apply_workspace_size(M, nrhs)
+ *                 bytes (scratch; its status word is read by hqr_status).
+ * Asynchronous on `stream`, which must be the factorization's stream or
+ * ordered after it.  Errors: -2 M < N or M < 1, -3 N < 1, -4 bad params,
+ * -6 dwork NULL, -7 work_bytes too small for (M, N), -8 dB NULL,
+ * -9 ldb < M, -10 nrhs < 1, -11 bwork NULL, -12 bwork too small. */
+int hqr_apply_qt(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* exec, const void* dwork,
+                 size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
+                 void* stream);
+
+/* B <- Q B (the transformations in reverse order, each one untransposed).
+ * Arguments and errors as hqr_apply_qt. */
+int hqr_apply_q(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* exec, const void* dwork,
+                size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
+                void* stream);
+
+/* Least squares min ||A x - b|| for each column of B (M >= N, A of full
+ * rank): hqr_factor of A, B <- Q^T B, then x = R^{-1} (Q^T B)(0:N) by back
+ * substitution with the leading N x N block of R.  On return (after the
+ * stream) A holds the factorization as after hqr_factor, B(0:N, :) the
+ * solutions and B(N:M, :) the components of Q^T B whose norm is the
+ * residual norm.  dwork: hqr_workspace_size(M, N) bytes; bwork:
+ * hqr_apply_workspace_size(M, nrhs) bytes.  A zero diagonal entry of R is
+ * reported by hqr_status(bwork) as HQR_ERR_SINGULAR with detail[0] = its
+ * index (the solution is then not finite).  Errors: -1 dA NULL, -2 M < N or
+ * M < 1, -3 N < 1, -4 lda < M, -5 dB NULL, -6 ldb < M, -7 nrhs < 1, -8 bad
+ * params, -10 dwork NULL, -11 dwork too small, -12 bwork NULL, -13 bwork
+ * too small. */
+int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t ldb, int32_t nrhs,
+              const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* bwork,
+              size_t bwork_bytes, void* stream);
+
+/* Status word of the last launch that used the workspace `dwork` (a
+ * factorization workspace, or the bwork of hqr_apply_qt/_q/hqr_lstsq):
+ * waits for the stream (at most 300 s), then reports 0, HQR_ERR_WATCHDOG or
+ * (hqr_lstsq) HQR_ERR_SINGULAR in *status.  Returns HQR_ERR_TIMEOUT if the
+ * stream is still busy after the wait. */
 int hqr_status(const void* dwork, void* stream, int32_t* status);
 
 /* As hqr_status with an explicit time limit (<= 0: 300 s).  When the launch

@@ -5,18 +5,21 @@ this package only marshals arguments to it:
 
 * :func:`factor` -- QR of a column-major float64 device matrix through one
   persistent GPU launch driven by a hierarchical elimination tree;
+* :func:`apply_qt`, :func:`apply_q` -- B <- Q^T B and B <- Q B with a
+  finished factorization; :func:`lstsq` -- least squares through both;
 * :func:`elimlist`, :func:`validate`, :func:`dag_stats` -- the elimination
   lists and task graphs the library builds on the host.
 
 PyTorch supplies device memory and streams only.
 """
 from . import _lib
-from ._lib import (BINARY, CHAIN, FIBONACCI, FLAT, GREEDY, OPS, Exec, HQRError, Params, dag_stats, elimlist,
-                   make_exec, make_params, release_plans, validate, version, workspace_size)
+from ._lib import (BINARY, CHAIN, FIBONACCI, FLAT, GREEDY, OPS, Exec, HQRError, Params, apply_workspace_size,
+                   dag_stats, elimlist, make_exec, make_params, release_plans, validate, version, workspace_size)
 
 __all__ = ["FLAT", "BINARY", "GREEDY", "FIBONACCI", "CHAIN", "OPS", "Params", "Exec", "HQRError", "make_params",
-           "make_exec", "elimlist", "validate", "dag_stats", "workspace_size", "factor", "colmajor", "r_of",
-           "Workspace", "status", "release_plans", "version"]
+           "make_exec", "elimlist", "validate", "dag_stats", "workspace_size", "apply_workspace_size", "factor",
+           "apply_qt", "apply_q", "lstsq", "colmajor", "r_of", "Workspace", "ApplyWorkspace", "status",
+           "release_plans", "version"]
 
 
 def colmajor(t):
@@ -36,6 +39,40 @@ class Workspace:
     @property
     def ptr(self):
         return self.buf.data_ptr()
+
+
+class ApplyWorkspace:
+    """Device workspace for :func:`apply_qt`, :func:`apply_q` and :func:`lstsq`."""
+
+    def __init__(self, M, nrhs, params, device="cuda"):
+        import torch
+
+        self.bytes = apply_workspace_size(M, nrhs, params)
+        self.buf = torch.empty(self.bytes, dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self):
+        return self.buf.data_ptr()
+
+
+def _colmajor_args(X, name):
+    import torch
+
+    if X.dtype != torch.float64 or not X.is_cuda or X.dim() != 2:
+        raise ValueError("%s must be a 2-D float64 CUDA tensor" % name)
+    if X.stride(0) != 1:
+        raise ValueError("%s must be column-major (stride(0) == 1); use colmajor()" % name)
+    M, N = X.shape
+    return M, N, (X.stride(1) if N > 1 else max(M, 1))
+
+
+def _device_status(work, s, what, timeout_s=0.0):
+    st, info = _lib.status(work.ptr, s.cuda_stream, timeout_s=timeout_s, detail=True)
+    if st != 0:
+        err = HQRError(what + " (device)", st)
+        err.detail = info
+        raise err
+    return st
 
 
 def factor(A, params, exec_=None, work=None, stream=None, check=True, timeout_s=0.0):
@@ -60,6 +97,56 @@ def factor(A, params, exec_=None, work=None, stream=None, check=True, timeout_s=
             err.detail = info
             raise RuntimeError("%s; task %d waited on counter %d for %d, last saw %d" % ((err,) + tuple(info)))
     return work
+
+
+def _apply(trans, B, M, N, params, work, exec_, bwork, stream, check):
+    import torch
+
+    MB, nrhs, ldb = _colmajor_args(B, "B")
+    if MB != M:
+        raise ValueError("B must have M = %d rows" % M)
+    if bwork is None:
+        bwork = ApplyWorkspace(M, nrhs, params, device=B.device)
+    s = stream if stream is not None else torch.cuda.current_stream(B.device)
+    _lib.apply_ptr(trans, M, N, params, exec_, work.ptr, work.bytes, B.data_ptr(), ldb, nrhs, bwork.ptr, bwork.bytes,
+                   s.cuda_stream)
+    if check:
+        _device_status(bwork, s, "hqr_apply_qt" if trans else "hqr_apply_q")
+    return bwork
+
+
+def apply_qt(B, M, N, params, work, exec_=None, bwork=None, stream=None, check=True):
+    """B <- Q^T B in place (B column-major M x nrhs) with the factorization
+    of an M x N matrix held in ``work`` (returned by :func:`factor`)."""
+    return _apply(True, B, M, N, params, work, exec_, bwork, stream, check)
+
+
+def apply_q(B, M, N, params, work, exec_=None, bwork=None, stream=None, check=True):
+    """B <- Q B in place; see :func:`apply_qt`."""
+    return _apply(False, B, M, N, params, work, exec_, bwork, stream, check)
+
+
+def lstsq(A, B, params, exec_=None, work=None, bwork=None, stream=None, check=True):
+    """Least squares min ||A X - B|| in place: A (M x N) is overwritten by its
+    factorization, B (M x nrhs) by X in its first N rows and the residual
+    components of Q^T B below.  Returns (work, bwork)."""
+    import torch
+
+    M, N, lda = _colmajor_args(A, "A")
+    MB, nrhs, ldb = _colmajor_args(B, "B")
+    if MB != M:
+        raise ValueError("B must have M = %d rows" % M)
+    if work is None:
+        work = Workspace(M, N, params, device=A.device)
+    if bwork is None:
+        bwork = ApplyWorkspace(M, nrhs, params, device=A.device)
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    _lib.lstsq_ptr(A.data_ptr(), M, N, lda, B.data_ptr(), ldb, nrhs, params, exec_, work.ptr, work.bytes, bwork.ptr,
+                   bwork.bytes, s.cuda_stream)
+    if check:
+        _device_status(work, s, "hqr_lstsq (factorization)")
+        _device_status(bwork, s, "hqr_lstsq")
+    return work, bwork
 
 
 def status(work, stream=None):

@@ -1,6 +1,7 @@
 // C ABI of the tiled hierarchical QR library (declared in include/hqr.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -21,11 +22,12 @@ namespace {
 constexpr int64_t kDefaultSpinLimit = 20000000;  // polls of one counter (tens of seconds)
 constexpr int kCtrlWords = 64;                    // cursor, status, spare
 
+// order: 0/1 for factorization plans, 2 + trans for apply plans (nbc = B blocks).
 struct PlanKey {
-  int32_t mt, nt, nb, p, a, low, high, coupling, domino, order, device;
+  int32_t mt, nt, nb, p, a, low, high, coupling, domino, order, device, nbc;
   bool operator<(const PlanKey& o) const {
-    return std::tie(mt, nt, nb, p, a, low, high, coupling, domino, order, device) <
-           std::tie(o.mt, o.nt, o.nb, o.p, o.a, o.low, o.high, o.coupling, o.domino, o.order, o.device);
+    return std::tie(mt, nt, nb, p, a, low, high, coupling, domino, order, device, nbc) <
+           std::tie(o.mt, o.nt, o.nb, o.p, o.a, o.low, o.high, o.coupling, o.domino, o.order, o.device, o.nbc);
   }
 };
 
@@ -103,10 +105,12 @@ Layout layout_for(int64_t M, int64_t N, const hqr_params& p) {
   return L;
 }
 
-int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan** out) {
+// Cached device plan: order 0/1 = factorization, 2 + trans = apply on nbc
+// blocks of B.
+int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan** out, int32_t nbc = 0) {
   int dev = 0;
   if (int rc = record_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
-  PlanKey key{mt, nt, p.nb, p.p, p.a, p.low, p.high, p.coupling, p.domino, order, dev};
+  PlanKey key{mt, nt, p.nb, p.p, p.a, p.low, p.high, p.coupling, p.domino, order, dev, nbc};
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {
@@ -114,7 +118,8 @@ int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan*
     return 0;
   }
   std::unique_ptr<DevicePlan> dp(new DevicePlan());
-  int rc = build_plan(mt, nt, p, order, chunks_for(p.nb), dp->plan);
+  int rc = order >= 2 ? build_apply_plan(mt, nt, nbc, p, order - 2, dp->plan)
+                      : build_plan(mt, nt, p, order, chunks_for(p.nb), dp->plan);
   if (rc) return rc;
   const size_t bytes = dp->plan.dev.size() * sizeof(DevTask);
   if (bytes) {
@@ -127,6 +132,83 @@ int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan*
   }
   *out = dp.get();
   g_plans[key] = std::move(dp);
+  return 0;
+}
+
+// Workspace of hqr_apply_qt/_q/hqr_lstsq: control words, one dependency
+// counter per block of B, and B in blocks of nb x 64.
+struct ApplyLayout {
+  int32_t mt, nbc;
+  size_t ctrl, cnt, blocks, total;
+};
+
+ApplyLayout apply_layout_for(int64_t M, int64_t nrhs, const hqr_params& p) {
+  ApplyLayout L{};
+  L.mt = (int32_t)((M + p.nb - 1) / p.nb);
+  L.nbc = (int32_t)((nrhs + 63) / 64);
+  size_t off = 0;
+  L.ctrl = off; off = align256(off + kCtrlWords * sizeof(int32_t));
+  L.cnt = off; off = align256(off + (size_t)L.mt * L.nbc * sizeof(int32_t));
+  L.blocks = off; off = align256(off + (size_t)L.mt * L.nbc * p.nb * 64 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// B (M x nrhs) <- Q^T B (trans = 1) or Q B with the factorization held in
+// dwork; B is copied into the blocks of bwork, transformed, and copied back
+// when copy_out.
+int run_apply(int trans, int64_t M, int64_t N, const hqr_params& p, const hqr_exec* exec, const void* dwork,
+              size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
+              void* stream, bool copy_out) {
+  const Layout L = layout_for(M, N, p);
+  const ApplyLayout AL = apply_layout_for(M, nrhs, p);
+  if (L.mt > 65535 || L.nt > 65535 || AL.nbc > 65535) return -2;
+  if (work_bytes < L.total) return -7;
+  if (bwork_bytes < AL.total) return -12;
+  hqr_exec ex{0, 0, 0};
+  if (exec) ex = *exec;
+  DevicePlan* dp = nullptr;
+  int rc = get_plan(L.mt, L.nt, p, 2 + trans, &dp, AL.nbc);
+  if (rc) return rc;
+  const char* w = (const char*)dwork;
+  char* bw = (char*)bwork;
+  LaunchArgs a{};
+  a.A = (double*)(w + L.tiles);
+  a.lda = p.nb;
+  a.Tg = (double*)(w + L.tg);
+  a.Tk = (double*)(w + L.tk);
+  a.ctrl = (int32_t*)(bw + AL.ctrl);
+  a.cnt = (int32_t*)(bw + AL.cnt);
+  a.B = (double*)(bw + AL.blocks);
+  a.tasks = dp->d_tasks;
+  a.ntasks = (int64_t)dp->plan.dev.size();
+  a.spin_limit = ex.spin_limit > 0 ? ex.spin_limit : kDefaultSpinLimit;
+  a.mt = L.mt;
+  a.nt = L.nt;
+  a.chunks = 1;
+  a.cnt_cols = AL.nbc;
+  a.trans = trans;
+  if ((rc = launch_tile_copy(dB, ldb, a.B, M, nrhs, p.nb, 64, AL.mt, AL.nbc, true, stream))) return rc;
+  const int64_t nwords = (int64_t)((AL.blocks - AL.ctrl) / sizeof(int32_t));  // ctrl + counters
+  if ((rc = launch_zero_i32(a.ctrl, nwords, stream))) return rc;
+  if (a.ntasks > 0) {
+    int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb);
+    if ((rc = launch_persistent(p.nb, a, workers, stream))) return rc;
+  }
+  if (copy_out && (rc = launch_tile_copy(dB, ldb, a.B, M, nrhs, p.nb, 64, AL.mt, AL.nbc, false, stream))) return rc;
+  return 0;
+}
+
+int check_apply_args(int64_t M, int64_t N, const hqr_params* params, const void* dwork, const double* dB,
+                     int64_t ldb, int32_t nrhs, const void* bwork) {
+  if (M < 1 || M < N) return -2;
+  if (N < 1) return -3;
+  if (!params || check_params(*params)) return -4;
+  if (!dwork) return -6;
+  if (!dB) return -8;
+  if (ldb < M) return -9;
+  if (nrhs < 1) return -10;
+  if (!bwork) return -11;
   return 0;
 }
 
@@ -240,15 +322,70 @@ int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* 
   a.mt = L.mt;
   a.nt = L.nt;
   a.chunks = L.chunks;
+  a.cnt_cols = L.nt;
+  a.B = nullptr;
   a.A = (double*)(w + L.tiles);
   a.lda = p.nb;
-  if ((rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, L.mt, L.nt, true, stream))) return rc;
+  if ((rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, p.nb, L.mt, L.nt, true, stream))) return rc;
   const int64_t nwords = (int64_t)((L.tg - L.ctrl) / sizeof(int32_t));  // ctrl + counters
   if ((rc = launch_zero_i32(a.ctrl, nwords, stream))) return rc;
   int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb);
   if ((rc = launch_persistent(p.nb, a, workers, stream))) return rc;
-  if ((rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, L.mt, L.nt, false, stream))) return rc;
+  if ((rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, p.nb, L.mt, L.nt, false, stream))) return rc;
   return 0;
+}
+
+int hqr_apply_workspace_size(int64_t M, int32_t nrhs, const hqr_params* params, size_t* bytes) {
+  if (M < 1) return -1;
+  if (nrhs < 1) return -2;
+  if (!params || check_params(*params)) return -3;
+  if (!bytes) return -4;
+  *bytes = apply_layout_for(M, nrhs, *params).total;
+  return 0;
+}
+
+int hqr_apply_qt(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* exec, const void* dwork,
+                 size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
+                 void* stream) {
+  if (int rc = check_apply_args(M, N, params, dwork, dB, ldb, nrhs, bwork)) return rc;
+  return run_apply(1, M, N, *params, exec, dwork, work_bytes, dB, ldb, nrhs, bwork, bwork_bytes, stream, true);
+}
+
+int hqr_apply_q(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* exec, const void* dwork,
+                size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
+                void* stream) {
+  if (int rc = check_apply_args(M, N, params, dwork, dB, ldb, nrhs, bwork)) return rc;
+  return run_apply(0, M, N, *params, exec, dwork, work_bytes, dB, ldb, nrhs, bwork, bwork_bytes, stream, true);
+}
+
+int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t ldb, int32_t nrhs,
+              const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* bwork,
+              size_t bwork_bytes, void* stream) {
+  if (!dA) return -1;
+  if (M < 1 || M < N) return -2;
+  if (N < 1) return -3;
+  if (lda < M) return -4;
+  if (!dB) return -5;
+  if (ldb < M) return -6;
+  if (nrhs < 1) return -7;
+  if (!params || check_params(*params)) return -8;
+  if (!dwork) return -10;
+  if (!bwork) return -12;
+  int rc = hqr_factor(dA, M, N, lda, params, exec, dwork, work_bytes, stream);
+  if (rc) return rc > 0 ? rc : (rc == -7 ? -10 : rc == -8 ? -11 : rc);
+  const hqr_params& p = *params;
+  rc = run_apply(1, M, N, p, exec, dwork, work_bytes, dB, ldb, nrhs, bwork, bwork_bytes, stream, false);
+  if (rc) return rc > 0 ? rc : (rc == -12 ? -13 : rc);
+  const Layout L = layout_for(M, N, p);
+  const ApplyLayout AL = apply_layout_for(M, nrhs, p);
+  const char* w = (const char*)dwork;
+  char* bw = (char*)bwork;
+  double* blocks = (double*)(bw + AL.blocks);
+  const int groups = (int)std::min<int64_t>(4, (nrhs + 15) / 16);
+  if ((rc = launch_trsm(p.nb, (const double*)(w + L.tiles), blocks, (int32_t*)(bw + AL.ctrl), N, L.mt, L.nt, AL.nbc,
+                        AL.nbc > 1 ? 4 : groups, stream)))
+    return rc;
+  return launch_tile_copy(dB, ldb, blocks, M, nrhs, p.nb, 64, AL.mt, AL.nbc, false, stream);
 }
 
 int hqr_status(const void* dwork, void* stream, int32_t* status) {
@@ -290,11 +427,16 @@ int hqr_status_ex(const void* dwork, void* stream, double timeout_s, int32_t* st
     }
     std::this_thread::sleep_for(std::chrono::microseconds(dt < 0.01 ? 20 : 1000));
   }
-  int32_t ctrl[6] = {0, 0, 0, 0, 0, 0};
+  int32_t ctrl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (int rc = record_hip(hipMemcpy(ctrl, dwork, sizeof(ctrl), hipMemcpyDeviceToHost), "hipMemcpy(status)")) return rc;
   *status = ctrl[1];
-  if (detail)
+  if (detail) {
     for (int q = 0; q < 4; ++q) detail[q] = ctrl[2 + q];
+    if (ctrl[1] == HQR_ERR_SINGULAR) {
+      detail[0] = ctrl[7] - ctrl[6];  // first zero diagonal entry of R
+      detail[1] = detail[2] = detail[3] = 0;
+    }
+  }
   return 0;
 }
 
@@ -316,6 +458,7 @@ const char* hqr_strerror(int code) {
     case HQR_ERR_INTERNAL: return "internal error";
     case HQR_ERR_INVALID_LIST: return "elimination list breaks the validity rules";
     case HQR_ERR_TIMEOUT: return "the GPU work did not finish within the time limit";
+    case HQR_ERR_SINGULAR: return "R has a zero diagonal entry (A is rank deficient)";
     default: return "unknown error";
   }
 }

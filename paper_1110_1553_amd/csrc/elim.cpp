@@ -442,4 +442,53 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
   return 0;
 }
 
+int build_apply_plan(int32_t mt, int32_t nt, int32_t nbc, const hqr_params& prm, int trans, Plan& plan) {
+  plan = Plan();
+  plan.mt = mt;
+  plan.nt = nt;
+  plan.nb = prm.nb;
+  plan.chunks = 1;
+  plan.list = make_elimlist(mt, nt, prm);
+  if (!validate_elimlist(mt, nt, plan.list.data(), (int64_t)plan.list.size()).empty()) return HQR_ERR_INTERNAL;
+  // the transformations that act on B: one per triangularisation (GEQRT ->
+  // UNMQR) and one per elimination (TSQRT -> TSMQR, TTQRT -> TTMQR)
+  std::vector<Task> ops;
+  for (const Task& t : expand_tasks(mt, std::max(nt, 1), plan.list)) {
+    if (t.op == GEQRT) ops.push_back({UNMQR, t.row, -1, t.k, -1});
+    if (t.op == TSQRT) ops.push_back({TSMQR, t.row, t.killer, t.k, -1});
+    if (t.op == TTQRT) ops.push_back({TTMQR, t.row, t.killer, t.k, -1});
+  }
+  if (!trans) std::reverse(ops.begin(), ops.end());
+  std::vector<uint32_t> writes((size_t)mt * nbc, 0);
+  plan.dev.reserve(ops.size() * nbc);
+  for (const Task& t : ops) {
+    for (int32_t b = 0; b < nbc; ++b) {
+      DevTask d{};
+      d.op = t.op;
+      d.chunk = 0;
+      d.row = (uint16_t)t.row;
+      d.killer = (uint16_t)(t.op == UNMQR ? t.row : t.killer);
+      d.k = (uint16_t)t.k;
+      d.j = (uint16_t)b;
+      d.v[0] = 0;
+      const size_t xi = (size_t)t.row * nbc + b;
+      if (t.op == UNMQR) {
+        d.v[1] = writes[xi];
+      } else {
+        const size_t xp = (size_t)t.killer * nbc + b;
+        d.v[1] = writes[xp];
+        d.v[2] = writes[xi];
+        writes[xp]++;
+      }
+      writes[xi]++;
+      plan.dev.push_back(d);
+      plan.info.count[t.op]++;
+      plan.info.weight += op_weight(t.op);
+    }
+  }
+  plan.info.eliminations = (int64_t)plan.list.size();
+  plan.info.tasks = plan.info.device_tasks = (int64_t)plan.dev.size();
+  return 0;
+}
+
 }  // namespace hqr

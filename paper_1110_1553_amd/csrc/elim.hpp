@@ -81,4 +81,13 @@ struct Plan {
 // program order.  `chunks` = column chunks per update task.
 int build_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, int chunks, Plan& plan);
 
+// Device plan of B <- Q^T B (trans = 1) or B <- Q B (trans = 0) for the
+// factorization of an mt x nt tile grid, on a B of mt tile rows and `nbc`
+// blocks of 64 columns.  The update tasks of the factorization (UNMQR,
+// TSMQR, TTMQR) are replayed on B's blocks, in program order for Q^T and in
+// reverse program order for Q.  A task's `j` is the B block; its counters are
+// indexed (row * nbc + j), one per block; v[0] (the factored tile) is 0
+// because the factorization has finished.
+int build_apply_plan(int32_t mt, int32_t nt, int32_t nbc, const hqr_params& p, int trans, Plan& plan);
+
 }  // namespace hqr

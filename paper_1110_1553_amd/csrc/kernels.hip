@@ -90,6 +90,15 @@ struct Smem {
   int ok;    // 1 if the task's dependencies were met, 0 if the launch was aborted
 };
 
+// The scheduler's shared state and the tile kernels' staging buffers live in
+// the launch's dynamic LDS.
+extern __shared__ __attribute__((aligned(16))) double hqr_lds[];
+
+template <int NB>
+__device__ __forceinline__ Smem<NB>& smem() {
+  return *reinterpret_cast<Smem<NB>*>(hqr_lds);
+}
+
 // Lane coordinates.
 struct Lane {
   int wave, g, q, pq;
@@ -109,7 +118,7 @@ struct Lane {
 // the strip of the killer tile (rows 16p..16p+15) for TS/TT, or null.
 //
 //   W  = V_p^T acc (+ C1_p)      reduction over the active rows
-//   W  = T_p^T W
+//   W  = T_p^T W                  (T_p W when applying Q instead of Q^T)
 //   C1_p -= W,   acc -= V_p W
 //
 // Active rows: UNM rows >= 16p (V unit lower triangular), TS all rows
@@ -124,7 +133,7 @@ __device__ __forceinline__ bool row_block_active(int rb, int p) {
 // MFMAs of the current one; scheduling barriers keep the compiler from
 // hoisting all operand loads at once, which would not fit next to the
 // accumulators.  Consecutive MFMAs never write the same accumulator.
-template <int NB, int KIND>
+template <int NB, int KIND, bool TRANS = true>
 __device__ __forceinline__ void apply_panel(d4 (&acc)[NB / 16], const double* __restrict__ Vs,
                                             const double* __restrict__ Ts, int p, double* c1,
                                             int64_t ldc, const Lane& L) {
@@ -167,7 +176,8 @@ __device__ __forceinline__ void apply_panel(d4 (&acc)[NB / 16], const double* __
   if (KIND != K_UNM) w += c1v;
   d4 w2t = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int r = 0; r < 4; ++r) w2t = mfma(Ts[(4 * L.g + r) * LDV + L.pq], w[r], w2t);
+  for (int r = 0; r < 4; ++r)
+    w2t = mfma(TRANS ? Ts[(4 * L.g + r) * LDV + L.pq] : Ts[L.pq * LDV + 4 * L.g + r], w[r], w2t);
   if (KIND != K_UNM) st4(c1 + 4 * L.g + (int64_t)L.q * ldc, c1v - w2t);
   const d4 wn = -w2t;
   // ---- acc -= V W: groups of two row blocks, products interleaved
@@ -271,23 +281,30 @@ __device__ __forceinline__ void stage_panel(const PanelPrefetch<NB>& pf, double*
 //   V, T: the factored tile and its T (block column nb x 16).
 //   C2: tile updated below the identity part (UNM: the tile itself).
 //   C1: killer tile (TS/TT).
-template <int NB, int KIND>
+// TRANS applies Q^T (the panels in factorization order, T^T); otherwise Q
+// (the panels in reverse order, T).
+template <int NB, int KIND, bool TRANS>
 __device__ __forceinline__ void run_update(Smem<NB>& sm, const double* V, const double* T, double* C1, double* C2,
-                           int64_t ld) {
+                                           int64_t ld) {
   constexpr int NP = NB / IB;
   const Lane L;
   d4 acc[NB / 16];
   const int64_t coloff = (int64_t)(16 * L.wave) * ld;
   load_strip<NB, K_TS>(acc, C2 + coloff, ld, 0, L);
   PanelPrefetch<NB> pf;
-  prefetch_panel<NB, KIND>(pf, V, ld, T, 0);
-  for (int p = 0; p < NP; ++p) {
-    double* Vs = sm.V[p & 1];
-    double* Ts = sm.T[p & 1];
+  const int pfirst = TRANS ? 0 : NP - 1;
+  prefetch_panel<NB, KIND>(pf, V, ld, T + pfirst * 256, pfirst);
+  for (int it = 0; it < NP; ++it) {
+    const int p = TRANS ? it : NP - 1 - it;
+    double* Vs = sm.V[it & 1];
+    double* Ts = sm.T[it & 1];
     stage_panel<NB, KIND>(pf, Vs, Ts, p);
     __syncthreads();
-    if (p + 1 < NP) prefetch_panel<NB, KIND>(pf, V, ld, T + (p + 1) * 256, p + 1);
-    apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p, ld, L);
+    if (it + 1 < NP) {
+      const int pn = TRANS ? p + 1 : p - 1;
+      prefetch_panel<NB, KIND>(pf, V, ld, T + pn * 256, pn);
+    }
+    apply_panel<NB, KIND, TRANS>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p, ld, L);
   }
   store_strip<NB, K_TS>(acc, C2 + coloff, ld, 0, L);
 }
@@ -305,147 +322,238 @@ __device__ __forceinline__ void run_update(Smem<NB>& sm, const double* V, const 
 // otherwise beta = -sign(alpha) sqrt(alpha^2 + s^2), tau = (beta - alpha)/beta,
 // tail /= (alpha - beta), head = beta.
 //
-// The 16 columns of a panel stay in registers during the column loop:
-// thread (cc, q) = (tid / 16, tid % 16) holds column c0 + cc at the rows
-// base + q + 16 m (base = c0 for GEQRT, 0 otherwise), so the reductions over
-// rows are 16-lane shuffles inside one wavefront.  The only data crossing
-// groups is the reflector being applied, published through LDS (double
-// buffered), which costs one workgroup barrier per column.
+// The tile is processed in blocks of 64 columns (four 16-column panels).
+// Inside a block each panel is factored (panel_columns) and applied to the
+// block's remaining strips (panel_strips); at the end of a block its four
+// panels are applied to the columns right of the block, 64 columns at a
+// time with the strips held in registers across the four panels
+// (panel_block_update), so those columns are read and written once per
+// block instead of once per panel.  The phases are separate functions so
+// each gets its own register allocation.
+
+// Reads lane `lane` (wave-uniform) of a double held in VGPRs.
+__device__ __forceinline__ double readlane(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Factors panel p (columns c0 = 16p .. c0+15).  The 16 columns stay in
+// registers during the column loop: thread (cc, q) = (tid / 16, tid % 16)
+// holds column c0 + cc at the rows base + q + 16 m (base = c0 for GEQRT,
+// 0 otherwise), so the reductions over rows are 16-lane DPP sums inside one
+// wavefront.  The only data crossing groups is the reflector being applied,
+// published through LDS (double buffered), which costs one workgroup
+// barrier per column.  Leaves V_p in sm.V[0] (with the structure of the
+// kind), T_p in sm.T[0] and in `T`, and the factored columns in A (and R).
 template <int NB, int KIND>
-__device__ __forceinline__ void run_panel(Smem<NB>& sm, double* A, double* R, double* T, int64_t ld) {
-  constexpr int NP = NB / IB;
-  constexpr int NM = NB / 16;  // rows per thread
+__device__ __noinline__ void panel_columns(double* A, double* R, double* T, int p) {
+  constexpr int NM = NB / 16;  // row slots per thread
+  Smem<NB>& sm = smem<NB>();
   const int tid = threadIdx.x;
-  const Lane L;
-  const int cc = tid >> 4;   // panel column of this thread
-  const int q = tid & 15;    // its rows are base + q + 16 m
+  const int cc = tid >> 4;  // panel column of this thread
+  const int q = tid & 15;   // its rows are base + q + 16 m
+  const int c0 = 16 * p;
+  const int base = (KIND == K_UNM) ? c0 : 0;
+  // row slots that can hold rows of the panel (uniform): GEQRT rows < NB,
+  // TT rows <= c0 + 15
+  const int nm = (KIND == K_UNM) ? NM - p : (KIND == K_TT ? p + 1 : NM);
   double* Vs = sm.V[0];
   double* Ts = sm.T[0];
-  double* Zs = sm.R;         // Gram entries v_i^T v_j of the panel
-  double* Vb = sm.V[1];      // published reflector, two buffers of NB
-  for (int p = 0; p < NP; ++p) {
-    const int c0 = 16 * p;
-    const int base = (KIND == K_UNM) ? c0 : 0;
-    // ---- the panel into registers (inactive rows: zero, never stored)
-    double x[NM];
+  double* Zs = sm.R;     // Gram entries v_i^T v_j of the panel
+  double* Vb = sm.V[1];  // published reflector, two buffers of NB
+  double* col = A + (int64_t)(c0 + cc) * NB;
+  double x[NM];
 #pragma unroll
-    for (int m = 0; m < NM; ++m) {
-      const int r = base + q + 16 * m;
-      bool act = r < NB;
-      if (KIND == K_TT) act = r <= c0 + cc;  // below: the tile's stored GEQRT reflectors
-      x[m] = act ? A[r + (int64_t)(c0 + cc) * ld] : 0.0;
-    }
-    double rv = 0.0;  // TS/TT: R(c0 + q, c0 + cc) of the killer's diagonal block
-    if (KIND != K_UNM && q <= cc) rv = R[(c0 + q) + (int64_t)(c0 + cc) * ld];
-    Zs[cc * LDV + q] = 0.0;  // entries (i, j) with i >= j stay zero
-    // ---- unblocked factorization, one reflector per column
-    for (int jj = 0; jj < 16; ++jj) {
-      const int j = c0 + jj;
-      double* vb = Vb + (jj & 1) * NB;
-      if (cc == jj) {
-        const double alpha = (KIND == K_UNM) ? __shfl(x[0], jj, 16) : __shfl(rv, jj, 16);
-        double ss = 0.0;
+  for (int m = 0; m < NM; ++m) {
+    const int r = base + q + 16 * m;
+    // TT: rows below the diagonal hold the tile's own GEQRT reflectors
+    const bool act = m < nm && (KIND != K_TT || r <= c0 + cc);
+    x[m] = act ? col[r] : 0.0;
+  }
+  double rv = 0.0;  // TS/TT: R(c0 + q, c0 + cc) of the killer's diagonal block
+  if (KIND != K_UNM && q <= cc) rv = R[(c0 + q) + (int64_t)(c0 + cc) * NB];
+  Zs[cc * LDV + q] = 0.0;  // entries (i, j) with i >= j stay zero
+  for (int jj = 0; jj < 16; ++jj) {
+    double* vb = Vb + (jj & 1) * NB;
+    if (cc == jj) {
+      // the group owning column jj: wave jj / 4, lanes 16 (jj % 4) .. + 15;
+      // the head is in its lane q = jj (GEQRT: slot 0; TS/TT: rv)
+      const double alpha = readlane(KIND == K_UNM ? x[0] : rv, (jj & 3) * 16 + jj);
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-        for (int m = 0; m < NM; ++m) {
-          const int r = base + q + 16 * m;
-          const bool tail = (KIND == K_UNM) ? (r > j && r < NB) : (KIND == K_TT ? r <= j : true);
-          if (tail) ss += x[m] * x[m];
+      for (int m = 0; m < NM; ++m) {
+        if (m < nm) {
+          double t = x[m];
+          if (KIND == K_UNM && m == 0 && q <= jj) t = 0.0;  // rows <= j are not in the tail
+          if ((m & 3) == 0) s0 += t * t;
+          if ((m & 3) == 1) s1 += t * t;
+          if ((m & 3) == 2) s2 += t * t;
+          if ((m & 3) == 3) s3 += t * t;
         }
-        ss = sum16(ss);
-        double tau = 0.0, beta = alpha, scale = 1.0;
-        if (ss != 0.0) {
-          beta = sqrt(alpha * alpha + ss);
-          if (alpha >= 0.0) beta = -beta;
-          tau = (beta - alpha) / beta;
-          scale = 1.0 / (alpha - beta);
-        }
-#pragma unroll
-        for (int m = 0; m < NM; ++m) {
-          const int r = base + q + 16 * m;
-          const bool tail = (KIND == K_UNM) ? (r > j && r < NB) : (KIND == K_TT ? r <= j : true);
-          const bool head = (KIND == K_UNM) && r == j;
-          if (tail) x[m] *= scale;
-          if (head) x[m] = beta;
-          if (base + q + 16 * m < NB) vb[q + 16 * m] = tail ? x[m] : (head ? 1.0 : 0.0);
-        }
-        if (KIND != K_UNM && q == jj) rv = beta;
-        if (q == 0) sm.tau[jj] = tau;
       }
-      __syncthreads();
-      if (cc != jj) {
-        const double tau = sm.tau[jj];
-        double v[NM];
-        double d = 0.0;
+      const double ss = sum16((s0 + s1) + (s2 + s3));
+      double tau = 0.0, beta = alpha, scale = 1.0;
+      if (ss != 0.0) {
+        beta = sqrt(alpha * alpha + ss);
+        if (alpha >= 0.0) beta = -beta;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
 #pragma unroll
-        for (int m = 0; m < NM; ++m) {
-          v[m] = (base + q + 16 * m < NB) ? vb[q + 16 * m] : 0.0;
-          d += v[m] * x[m];
-        }
-        d = sum16(d);
-        if (KIND != K_UNM && cc > jj) d += __shfl(rv, jj, 16);  // R(j, c0+cc) meets the unit entry of v
-        if (cc > jj) {
-          if (tau != 0.0) {
-            const double f = tau * d;
-#pragma unroll
-            for (int m = 0; m < NM; ++m) x[m] -= f * v[m];
-            if (KIND != K_UNM && q == jj) rv -= f;
+      for (int m = 0; m < NM; ++m) {
+        if (m < nm) {
+          if (KIND == K_UNM && m == 0) {
+            if (q > jj) x[0] *= scale;
+            if (q == jj) x[0] = beta;
+            vb[q] = (q > jj) ? x[0] : (q == jj ? 1.0 : 0.0);
+          } else {
+            x[m] *= scale;
+            vb[q + 16 * m] = x[m];
           }
-        } else if (q == 0) {
-          Zs[cc * LDV + jj] = d;  // v_cc^T v_jj, consumed when T is formed
         }
       }
+      if (KIND != K_UNM && q == jj) rv = beta;
+      if (q == 0) sm.tau[jj] = tau;
     }
     __syncthreads();
-    // ---- T: T(jj,jj) = tau_jj, T(0:jj, jj) = -tau_jj T(0:jj,0:jj) (V^T v_jj)(0:jj)
-    //      (Schreiber-Van Loan forward recurrence, one row of T per lane)
-    if (tid < 16) {
-      const int i = tid;
-      double trow[16];
+    if (cc != jj) {
+      const double tau = sm.tau[jj];
+      double v[NM];
+      double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
 #pragma unroll
-      for (int jj = 0; jj < 16; ++jj) trow[jj] = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj) {
-        const double tj = sm.tau[jj];
-        double zc[16];
-#pragma unroll
-        for (int qq = 0; qq < 16; ++qq) zc[qq] = Zs[qq * LDV + jj];  // zero for qq >= jj
-        double s = 0.0;
-#pragma unroll
-        for (int qq = 0; qq < 16; ++qq) s += ((qq < jj && qq >= i) ? trow[qq] : 0.0) * zc[qq];
-        trow[jj] = (i < jj) ? -tj * s : (i == jj ? tj : 0.0);
+      for (int m = 0; m < NM; ++m) {
+        v[m] = 0.0;
+        if (m < nm) {
+          v[m] = vb[q + 16 * m];
+          if ((m & 3) == 0) d0 += v[m] * x[m];
+          if ((m & 3) == 1) d1 += v[m] * x[m];
+          if ((m & 3) == 2) d2 += v[m] * x[m];
+          if ((m & 3) == 3) d3 += v[m] * x[m];
+        }
       }
+      // TS/TT: the unit entry of v sits in row j of the triangle on top,
+      // where lane q = jj of column c0 + cc holds R(j, c0 + cc)
+      if (KIND != K_UNM && cc > jj && q == jj) d0 += rv;
+      const double d = sum16((d0 + d1) + (d2 + d3));
+      if (cc > jj) {
+        if (tau != 0.0) {
+          const double f = tau * d;
 #pragma unroll
-      for (int jj = 0; jj < 16; ++jj) {
-        Ts[i * LDV + jj] = trow[jj];
-        T[p * 256 + i + 16 * jj] = trow[jj];
+          for (int m = 0; m < NM; ++m)
+            if (m < nm) x[m] -= f * v[m];
+          if (KIND != K_UNM && q == jj) rv -= f;
+        }
+      } else if (q == 0) {
+        Zs[cc * LDV + jj] = d;  // v_cc^T v_jj, consumed when T is formed
       }
     }
-    // ---- the factored panel back to the tiles, and the V of the block update into LDS
+  }
+  __syncthreads();
+  // ---- T: T(jj,jj) = tau_jj, T(0:jj, jj) = -tau_jj T(0:jj,0:jj) (V^T v_jj)(0:jj)
+  //      (Schreiber-Van Loan forward recurrence, one row of T per lane; the
+  //      sums for the later columns are accumulated as each entry appears)
+  if (tid < 16) {
+    const int i = tid;
+    double acc[16], t[16];
 #pragma unroll
-    for (int m = 0; m < NM; ++m) {
+    for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double tk = sm.tau[k];
+      t[k] = (i < k) ? -tk * acc[k] : (i == k ? tk : 0.0);
+#pragma unroll
+      for (int jj = k + 1; jj < 16; ++jj) acc[jj] += t[k] * Zs[k * LDV + jj];
+    }
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      Ts[i * LDV + jj] = t[jj];
+      T[p * 256 + i + 16 * jj] = t[jj];
+    }
+  }
+  // ---- the factored panel back to the tiles, and V_p into LDS
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    if (m < nm) {
       const int r = base + q + 16 * m;
-      bool act = r < NB;
-      if (KIND == K_TT) act = r <= c0 + cc;
+      const bool act = KIND != K_TT || r <= c0 + cc;
       if (act) {
-        A[r + (int64_t)(c0 + cc) * ld] = x[m];
+        col[r] = x[m];
         double vv = x[m];
-        if (KIND == K_UNM && r <= c0 + cc) vv = (r == c0 + cc) ? 1.0 : 0.0;  // unit diagonal, R above
+        if (KIND == K_UNM && m == 0 && q <= cc) vv = (q == cc) ? 1.0 : 0.0;  // unit diagonal, R above
         Vs[r * LDV + cc] = vv;
-      } else if (KIND == K_TT && r < c0 + 16) {
-        Vs[r * LDV + cc] = 0.0;
+      } else {
+        Vs[r * LDV + cc] = 0.0;  // TT: zero below the diagonal of V
       }
     }
-    if (KIND != K_UNM && q <= cc) R[(c0 + q) + (int64_t)(c0 + cc) * ld] = rv;
-    __syncthreads();
-    // ---- apply the panel's block reflector to the remaining columns
-    for (int s = p + 1 + L.wave; s < NP; s += 4) {
-      d4 acc[NB / 16];
-      double* strip = A + (int64_t)(16 * s) * ld;
-      load_strip<NB, KIND>(acc, strip, ld, p, L);
-      apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * ld + c0, ld, L);
-      store_strip<NB, KIND>(acc, strip, ld, p, L);
+  }
+  if (KIND != K_UNM && q <= cc) R[(c0 + q) + (int64_t)(c0 + cc) * NB] = rv;
+  __syncthreads();
+}
+
+// Applies panel p (V_p, T_p staged in sm.V[0], sm.T[0]) to the strips
+// p+1 .. s_last of the tile(s) (at most 3): wave w takes strip p + 1 + w.
+template <int NB, int KIND>
+__device__ __noinline__ void panel_strips(double* A, double* R, int p, int s_last) {
+  Smem<NB>& sm = smem<NB>();
+  const Lane L;
+  const int s = p + 1 + L.wave;
+  if (s <= s_last) {
+    d4 acc[NB / 16];
+    double* strip = A + (int64_t)(16 * s) * NB;
+    load_strip<NB, KIND>(acc, strip, NB, p, L);
+    apply_panel<NB, KIND>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p,
+                          NB, L);
+    store_strip<NB, KIND>(acc, strip, NB, p, L);
+  }
+  __syncthreads();
+}
+
+// Applies the four panels of block b (panels 4b .. 4b+3, V from the tile,
+// T from `T`) to the columns right of the block, 64 at a time: wave w holds
+// strip 4c + w of chunk c in registers across the four panels.
+template <int NB, int KIND>
+__device__ __noinline__ void panel_block_update(double* A, double* R, const double* T, int b) {
+  constexpr int NRB = NB / 16;
+  Smem<NB>& sm = smem<NB>();
+  const Lane L;
+  const int p0 = 4 * b;
+  // row blocks any of the four panels touches
+  const int lo = (KIND == K_UNM) ? p0 : 0;
+  const int hi = (KIND == K_TT) ? p0 + 3 : NRB - 1;
+  for (int c = b + 1; c < NB / 64; ++c) {
+    const int s = 4 * c + L.wave;
+    double* strip = A + (int64_t)(16 * s) * NB;
+    d4 acc[NRB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+      if (rb >= lo && rb <= hi) acc[rb] = ld4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB);
+    PanelPrefetch<NB> pf;
+    prefetch_panel<NB, KIND>(pf, A, NB, T + p0 * 256, p0);
+    for (int p = p0; p < p0 + 4; ++p) {
+      double* Vs = sm.V[p & 1];
+      double* Ts = sm.T[p & 1];
+      stage_panel<NB, KIND>(pf, Vs, Ts, p);
+      __syncthreads();
+      if (p + 1 < p0 + 4) prefetch_panel<NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
+      apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
     }
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+      if (rb >= lo && rb <= hi) st4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB, acc[rb]);
     __syncthreads();
+  }
+}
+
+template <int NB, int KIND>
+__device__ __forceinline__ void run_panel(double* A, double* R, double* T) {
+  for (int b = 0; b < NB / 64; ++b) {
+    for (int p = 4 * b; p < 4 * b + 4; ++p) {
+      panel_columns<NB, KIND>(A, R, T, p);
+      if (p < 4 * b + 3) panel_strips<NB, KIND>(A, R, p, 4 * b + 3);
+    }
+    if (b + 1 < NB / 64) panel_block_update<NB, KIND>(A, R, T, b);
   }
 }
 
@@ -501,17 +609,8 @@ __device__ __forceinline__ void stamp(const LaunchArgs& a, int t, int slot) {
   }
 }
 
-// The scheduler's shared state and the tile kernels' staging buffers live in
-// the launch's dynamic LDS.
-extern __shared__ __attribute__((aligned(16))) double hqr_lds[];
-
-template <int NB>
-__device__ __forceinline__ Smem<NB>& smem() {
-  return *reinterpret_cast<Smem<NB>*>(hqr_lds);
-}
-
 __device__ __forceinline__ int32_t* counter(const LaunchArgs& a, int r, int c, int chunk) {
-  return a.cnt + ((int64_t)r * a.nt + c) * a.chunks + chunk;
+  return a.cnt + ((int64_t)r * a.cnt_cols + c) * a.chunks + chunk;
 }
 
 // The steps of one scheduler iteration are separate, non-inlined functions
@@ -627,21 +726,39 @@ __device__ __forceinline__ double* t_block(double* T, const LaunchArgs& a, int n
 }
 
 // One tile kernel per function (each gets its own register allocation).
+// Panel tasks are on the critical path of the factorization: their waves
+// run at raised priority so a co-resident update task yields issue slots.
 template <int NB, int KIND>
 __device__ __noinline__ void panel_task(const LaunchArgs& a, const DevTask& task) {
   double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
-  run_panel<NB, KIND>(smem<NB>(), tile_ptr(a, NB, task.row, task.k),
+  __builtin_amdgcn_s_setprio(2);
+  run_panel<NB, KIND>(tile_ptr(a, NB, task.row, task.k),
                       KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.k),
-                      t_block(T, a, NB, task.row, task.k), a.lda);
+                      t_block(T, a, NB, task.row, task.k));
+  __builtin_amdgcn_s_setprio(0);
 }
 
 template <int NB, int KIND>
 __device__ __noinline__ void update_task(const LaunchArgs& a, const DevTask& task) {
   double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
-  const int64_t colchunk = (int64_t)task.chunk * 64 * a.lda;
-  run_update<NB, KIND>(smem<NB>(), tile_ptr(a, NB, task.row, task.k), t_block(T, a, NB, task.row, task.k),
-                       KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.j) + colchunk,
-                       tile_ptr(a, NB, task.row, task.j) + colchunk, a.lda);
+  const int64_t colchunk = (int64_t)task.chunk * 64 * NB;
+  run_update<NB, KIND, true>(smem<NB>(), tile_ptr(a, NB, task.row, task.k), t_block(T, a, NB, task.row, task.k),
+                             KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.j) + colchunk,
+                             tile_ptr(a, NB, task.row, task.j) + colchunk, NB);
+}
+
+// Block of 64 columns of B (nb x 64, column-major) of tile row r.
+__device__ __forceinline__ double* b_block(const LaunchArgs& a, int nb, int r, int j) {
+  return a.B + ((int64_t)j * a.mt + r) * nb * 64;
+}
+
+// The same transformation applied to a block of B (hqr_apply_qt/_q).
+template <int NB, int KIND, bool TRANS>
+__device__ __noinline__ void apply_task(const LaunchArgs& a, const DevTask& task) {
+  double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
+  run_update<NB, KIND, TRANS>(smem<NB>(), tile_ptr(a, NB, task.row, task.k), t_block(T, a, NB, task.row, task.k),
+                              KIND == K_UNM ? nullptr : b_block(a, NB, task.killer, task.j),
+                              b_block(a, NB, task.row, task.j), NB);
 }
 
 // Persistent scheduler.  Workgroups take task indices from a global cursor
@@ -657,13 +774,29 @@ __global__ __launch_bounds__(NT, 2) void persistent_kernel(LaunchArgs a) {
     if (t < 0) break;
     const DevTask task = a.tasks[t];
     if (!wait_task<NB>(a, t, task)) break;
-    switch (task.op) {
-      case GEQRT: panel_task<NB, K_UNM>(a, task); break;
-      case TSQRT: panel_task<NB, K_TS>(a, task); break;
-      case TTQRT: panel_task<NB, K_TT>(a, task); break;
-      case UNMQR: update_task<NB, K_UNM>(a, task); break;
-      case TSMQR: update_task<NB, K_TS>(a, task); break;
-      default: update_task<NB, K_TT>(a, task); break;
+    if (a.B) {
+      if (a.trans) {
+        switch (task.op) {
+          case UNMQR: apply_task<NB, K_UNM, true>(a, task); break;
+          case TSMQR: apply_task<NB, K_TS, true>(a, task); break;
+          default: apply_task<NB, K_TT, true>(a, task); break;
+        }
+      } else {
+        switch (task.op) {
+          case UNMQR: apply_task<NB, K_UNM, false>(a, task); break;
+          case TSMQR: apply_task<NB, K_TS, false>(a, task); break;
+          default: apply_task<NB, K_TT, false>(a, task); break;
+        }
+      }
+    } else {
+      switch (task.op) {
+        case GEQRT: panel_task<NB, K_UNM>(a, task); break;
+        case TSQRT: panel_task<NB, K_TS>(a, task); break;
+        case TTQRT: panel_task<NB, K_TT>(a, task); break;
+        case UNMQR: update_task<NB, K_UNM>(a, task); break;
+        case TSMQR: update_task<NB, K_TS>(a, task); break;
+        default: update_task<NB, K_TT>(a, task); break;
+      }
     }
     finish_task<NB>(a, t, task);
   }
@@ -677,22 +810,105 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
     p[x] = 0;
 }
 
-// Column-major M x N matrix (leading dimension lda) <-> tiles of nb x nb
-// (tile (i, j) at index j * mt + i, column-major inside).  `in` fills the
-// tiles and zeroes the padding beyond M and N; `out` copies the M x N part
-// back.  One thread per element of the padded matrix, rows fastest.
-__global__ void tile_copy_kernel(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int mt, int nt,
-                                 int in) {
-  const int64_t Mp = (int64_t)mt * nb, total = Mp * (int64_t)nt * nb;
+// Column-major M x N matrix (leading dimension lda) <-> blocks of nb rows
+// x tw columns (block (i, j) at index j * mt + i, column-major inside with
+// leading dimension nb; tw = nb for the tiles of A, 64 for the blocks of
+// B).  `in` fills the blocks and zeroes the padding beyond M and N; `out`
+// copies the M x N part back.  One thread per element of the padded matrix,
+// rows fastest.
+__global__ void tile_copy_kernel(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int tw, int mt,
+                                 int nt, int in) {
+  const int64_t Mp = (int64_t)mt * nb, total = Mp * (int64_t)nt * tw;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = x % Mp, c = x / Mp;
-    const int64_t i = r / nb, j = c / nb;
-    double* t = At + ((j * mt + i) * nb + (c - j * nb)) * nb + (r - i * nb);
+    const int64_t i = r / nb, j = c / tw;
+    double* t = At + ((j * mt + i) * tw + (c - j * tw)) * nb + (r - i * nb);
     const bool inside = r < M && c < N;
     if (in)
       *t = inside ? A[r + c * lda] : 0.0;
     else if (inside)
       A[r + c * lda] = *t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Back substitution R x = y for tile row i of the leading N x N triangle
+// (least squares after B <- Q^T B).  R: the factored tiles (nb x nb,
+// tile-contiguous), Y: B in blocks of nb x 64; x overwrites y.  One
+// workgroup per (64-column block of B, group of 16 columns); thread r owns
+// row r of the tile row.  Rows at or beyond N are neither solved nor
+// written; x_j of rows >= N counts as zero.
+//   z = y_i - sum_{j > i} R_ij x_j           (x_j staged through LDS)
+//   z -> R_ii^{-1} z, 16 rows at a time: lanes 0..15 of wave 0 solve the
+//   16 x 16 diagonal block (lane = column), the rows above subtract it.
+// A zero diagonal entry R_jj is recorded in ctrl (status HQR_ERR_SINGULAR,
+// ctrl[6] = max over such j of N - j).
+template <int NB>
+__global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const double* R, double* Y, int32_t* ctrl, int64_t N,
+                                                           int mt, int nt, int i, int groups) {
+  double* xs = hqr_lds;  // x_j or z of this tile row: NB rows x 16 columns, stride 17 (dynamic LDS)
+  const int r = threadIdx.x;
+  const int blk = blockIdx.x / groups, grp = blockIdx.x % groups;
+  const int64_t row0 = (int64_t)i * NB;
+  const int nv = (int)((N - row0) < NB ? (N - row0) : NB);  // rows of this tile row inside N
+  double* Yb = Y + ((int64_t)blk * mt) * NB * 64 + 16 * grp * NB;  // column 16 grp of block blk
+  double z[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) z[c] = Yb[(int64_t)i * NB * 64 + r + (int64_t)c * NB];
+  for (int j = i + 1; j < nt; ++j) {
+    const int64_t jrow0 = (int64_t)j * NB;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const double xv = Yb[(int64_t)j * NB * 64 + r + (int64_t)c * NB];
+      xs[r * 17 + c] = (jrow0 + r < N) ? xv : 0.0;
+    }
+    __syncthreads();
+    const double* Rij = R + ((int64_t)j * mt + i) * NB * NB + r;
+    for (int k = 0; k < NB; ++k) {
+      const double rk = Rij[(int64_t)k * NB];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) z[c] -= rk * xs[k * 17 + c];
+    }
+  }
+  const double* Rii = R + ((int64_t)i * mt + i) * NB * NB;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 16; ++c) xs[r * 17 + c] = z[c];
+  __syncthreads();
+  for (int b = (nv - 1) / 16; b >= 0; --b) {
+    const int r0 = 16 * b;
+    if (r < 16) {
+      const int c = r;  // lane = column
+      for (int rr = r0 + 15; rr >= r0; --rr) {
+        if (rr >= nv) continue;
+        double t = xs[rr * 17 + c];
+        for (int k = rr + 1; k < r0 + 16 && k < nv; ++k) t -= Rii[rr + (int64_t)k * NB] * xs[k * 17 + c];
+        const double d = Rii[rr + (int64_t)rr * NB];
+        if (d == 0.0 && c == 0) {
+          int32_t none = 0;
+          __hip_atomic_compare_exchange_strong(&ctrl[1], &none, (int32_t)HQR_ERR_SINGULAR, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_max(&ctrl[6], (int32_t)(N - (row0 + rr)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&ctrl[7], (int32_t)N, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        xs[rr * 17 + c] = t / d;
+      }
+    }
+    __syncthreads();
+    if (r < r0) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double t = xs[r * 17 + c];
+        for (int k = r0; k < r0 + 16 && k < nv; ++k) t -= Rii[r + (int64_t)k * NB] * xs[k * 17 + c];
+        xs[r * 17 + c] = t;
+      }
+    }
+    __syncthreads();
+  }
+  if (r < nv) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) Yb[(int64_t)i * NB * 64 + r + (int64_t)c * NB] = xs[r * 17 + c];
   }
 }
 
@@ -720,12 +936,36 @@ int launch_zero_i32(int32_t* p, int64_t n, void* stream) {
   return record_hip(hipGetLastError(), "zero_i32_kernel launch");
 }
 
-int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int mt, int nt, bool in,
-                     void* stream) {
-  const int64_t total = (int64_t)mt * nb * (int64_t)nt * nb;
+int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int tw, int mt, int nt,
+                     bool in, void* stream) {
+  const int64_t total = (int64_t)mt * nb * (int64_t)nt * tw;
   hipLaunchKernelGGL(tile_copy_kernel, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, A, lda, At, M, N, nb,
-                     mt, nt, in ? 1 : 0);
+                     tw, mt, nt, in ? 1 : 0);
   return record_hip(hipGetLastError(), "tile_copy_kernel launch");
+}
+
+int launch_trsm(int nb, const double* R, double* Y, int32_t* ctrl, int64_t N, int mt, int nt, int nbc, int groups,
+                void* stream) {
+  for (int i = nt - 1; i >= 0; --i) {
+    const dim3 grid(nbc * groups), block(nb);
+    const size_t lds = (size_t)nb * 17 * sizeof(double);
+    switch (nb) {
+      case 64:
+        hipLaunchKernelGGL(trsm_tile_row_kernel<64>, grid, block, lds, (hipStream_t)stream, R, Y, ctrl, N, mt, nt, i,
+                           groups);
+        break;
+      case 128:
+        hipLaunchKernelGGL(trsm_tile_row_kernel<128>, grid, block, lds, (hipStream_t)stream, R, Y, ctrl, N, mt, nt, i,
+                           groups);
+        break;
+      default:
+        hipLaunchKernelGGL(trsm_tile_row_kernel<256>, grid, block, lds, (hipStream_t)stream, R, Y, ctrl, N, mt, nt, i,
+                           groups);
+        break;
+    }
+    if (int rc = record_hip(hipGetLastError(), "trsm_tile_row_kernel launch")) return rc;
+  }
+  return 0;
 }
 
 template <int NB>

@@ -22,7 +22,11 @@ struct LaunchArgs {
   int64_t spin_limit;
   int32_t* trace;     // optional host-visible progress words, 2 per workgroup (null: off)
   uint64_t* timeline; // optional per-task timestamps, 4 words per task (null: off)
+  double* B;          // hqr_apply_qt/_q: B in blocks of nb x 64 (block (r, j) at (j * mt + r) * nb * 64); null
+                      // for a factorization
   int32_t mt, nt, chunks;
+  int32_t cnt_cols;   // columns of the counter grid (nt, or the number of B blocks)
+  int32_t trans;      // apply: 1 = Q^T, 0 = Q
 };
 
 // Progress phases published per workgroup when tracing is on.
@@ -37,10 +41,16 @@ int launch_zero_i32(int32_t* p, int64_t n, void* stream);
 int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream);
 
 // Copies the column-major M x N matrix A (leading dimension lda) into the
-// tile-contiguous buffer At (mt x nt tiles of nb x nb, zero padding beyond M
-// and N) when `in`, or the M x N part of At back into A otherwise.
-int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int mt, int nt, bool in,
-                     void* stream);
+// blocked buffer At (mt x nt blocks of nb rows x tw columns, zero padding
+// beyond M and N) when `in`, or the M x N part of At back into A otherwise.
+int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int tw, int mt, int nt,
+                     bool in, void* stream);
+
+// Back substitution with the leading N x N triangle of the factored tiles R
+// on the first N rows of Y (blocks of nb x 64, nbc of them; `groups` groups
+// of 16 columns per block are solved), tile row by tile row.
+int launch_trsm(int nb, const double* R, double* Y, int32_t* ctrl, int64_t N, int mt, int nt, int nbc, int groups,
+                void* stream);
 
 // Stores "where: message" of a failed HIP call for hqr_last_error(); returns
 // HQR_ERR_HIP on failure, 0 on success.

@@ -64,3 +64,25 @@ def test_workspace_holds_padded_tile_copy(hqr_lib):
     assert ragged == aligned
     assert aligned >= 512 * 256 * 8 + 2 * 8 * 4 * 64 * 16 * 8
     assert h.workspace_size(513, 256, p) >= aligned + 4 * 64 * 64 * 8
+
+
+def test_apply_and_lstsq_argument_checks(hqr_lib):
+    import paper_1110_1553_amd as h
+
+    p = h.make_params(nb=64)
+    vp = ctypes.c_void_p
+    need = h.workspace_size(256, 128, p)
+    bneed = h.apply_workspace_size(256, 3, p)
+    assert bneed >= 256 * 64 * 8
+    args = lambda M, N, ldb, nrhs, wb, bb: (M, N, ctypes.byref(p), None, vp(16), wb, vp(16), ldb, nrhs, vp(16), bb, None)
+    for fn in (hqr_lib.hqr_apply_qt, hqr_lib.hqr_apply_q):
+        assert fn(*args(100, 200, 100, 1, need, bneed)) == -2       # M < N
+        assert fn(*args(256, 128, 200, 1, need, bneed)) == -9       # ldb < M
+        assert fn(*args(256, 128, 256, 0, need, bneed)) == -10      # nrhs < 1
+        assert fn(*args(256, 128, 256, 3, need - 1, bneed)) == -7   # factorization workspace too small
+        assert fn(*args(256, 128, 256, 3, need, bneed - 1)) == -12  # apply workspace too small
+    L = hqr_lib.hqr_lstsq
+    assert L(vp(16), 256, 128, 256, vp(16), 200, 1, ctypes.byref(p), None, vp(16), need, vp(16), bneed, None) == -6
+    assert L(vp(16), 256, 128, 256, vp(16), 256, 1, ctypes.byref(p), None, vp(16), need - 1, vp(16), bneed, None) == -11
+    with pytest.raises(h.HQRError):
+        h.apply_workspace_size(256, 0, p)
