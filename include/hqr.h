@@ -149,11 +149,13 @@ int hqr_dag_stats(int32_t mt, int32_t nt, const hqr_params* params, hqr_dag_info
  * 64-column chunk of an update task (tile columns are split into nb/64
  * chunks).  `row` is the tile row of GEQRT/UNMQR or the victim of a kill,
  * `killer` the killer row (= row for GEQRT/UNMQR), `k` the panel, `j` the
- * updated tile column (= k for panel tasks).  Before running, the task waits
+ * updated tile column (= k for panel tasks); for a panel task `chunk` is the
+ * number of column chunks of tile column k that hold matrix columns (chunks
+ * of zero padding are never touched).  Before running, the task waits
  * until the dependency counters of the tiles it touches reach v[0..2]:
- *   GEQRT  every chunk of (row,k) >= v0
+ *   GEQRT  chunks 0..chunk-1 of (row,k) >= v0
  *   UNMQR  (row,k) chunk 0 >= v0, (row,j) chunk `chunk` >= v1
- *   TSQRT/TTQRT  every chunk of (killer,k) >= v0 and of (row,k) >= v1
+ *   TSQRT/TTQRT  chunks 0..chunk-1 of (killer,k) >= v0 and of (row,k) >= v1
  *   TSMQR/TTMQR  (row,k) chunk 0 >= v0, (killer,j) and (row,j) chunk
  *                `chunk` >= v1 and v2
  * and afterwards bumps by one the counters of the tiles (chunks) it wrote. */
@@ -197,8 +199,8 @@ int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* b
 int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params,
                const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
 
-/* Bytes of the second workspace that hqr_apply_qt, hqr_apply_q and
- * hqr_lstsq need for a right-hand side B of M rows and nrhs columns: a
+/* Bytes of the second workspace that hqr_apply_qt and hqr_apply_q need for a
+ * right-hand side B of M rows and nrhs columns: a
  * status word, one dependency counter per block and B in blocks of nb rows x
  * 64 columns (zero-padded).  Errors: -1 M < 1, -2 nrhs < 1, -3 bad params. */
 int hqr_apply_workspace_size(int64_t M, int32_t nrhs, const hqr_params* params, size_t* bytes);
@@ -225,24 +227,30 @@ int hqr_apply_q(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* 
                 size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
                 void* stream);
 
+/* Bytes of device workspace hqr_lstsq needs: that of hqr_factor plus the
+ * right-hand sides as further (zero-padded) tile columns.  Errors: -1 M < N
+ * or M < 1, -2 N < 1, -3 nrhs < 1, -4 bad params. */
+int hqr_lstsq_workspace_size(int64_t M, int64_t N, int32_t nrhs, const hqr_params* params, size_t* bytes);
+
 /* Least squares min ||A x - b|| for each column of B (M >= N, A of full
- * rank): hqr_factor of A, B <- Q^T B, then x = R^{-1} (Q^T B)(0:N) by back
- * substitution with the leading N x N block of R.  On return (after the
- * stream) A holds the factorization as after hqr_factor, B(0:N, :) the
- * solutions and B(N:M, :) the components of Q^T B whose norm is the
- * residual norm.  dwork: hqr_workspace_size(M, N) bytes; bwork:
- * hqr_apply_workspace_size(M, nrhs) bytes.  A zero diagonal entry of R is
- * reported by hqr_status(bwork) as HQR_ERR_SINGULAR with detail[0] = its
+ * rank).  B is carried through the factorization as further tile columns,
+ * so the update kernels transform it by Q^T inside the same persistent
+ * launch (no second pass over the Householder vectors); then
+ * x = R^{-1} (Q^T B)(0:N) by back substitution with the leading N x N block
+ * of R (one launch per tile row).  On return (after the stream) A holds the
+ * factorization as after hqr_factor, B(0:N, :) the solutions and B(N:M, :)
+ * the components of Q^T B whose norm is the residual norm.  dwork:
+ * hqr_lstsq_workspace_size bytes; it also holds Q's factors for
+ * hqr_apply_qt with the same (M, N, params).  A zero diagonal entry of R is
+ * reported by hqr_status(dwork) as HQR_ERR_SINGULAR with detail[0] = its
  * index (the solution is then not finite).  Errors: -1 dA NULL, -2 M < N or
  * M < 1, -3 N < 1, -4 lda < M, -5 dB NULL, -6 ldb < M, -7 nrhs < 1, -8 bad
- * params, -10 dwork NULL, -11 dwork too small, -12 bwork NULL, -13 bwork
- * too small. */
+ * params, -9 bad exec.order, -10 dwork NULL, -11 dwork too small. */
 int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t ldb, int32_t nrhs,
-              const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* bwork,
-              size_t bwork_bytes, void* stream);
+              const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
 
 /* Status word of the last launch that used the workspace `dwork` (a
- * factorization workspace, or the bwork of hqr_apply_qt/_q/hqr_lstsq):
+ * factorization or least-squares workspace, or the bwork of hqr_apply_qt/_q):
  * waits for the stream (at most 300 s), then reports 0, HQR_ERR_WATCHDOG or
  * (hqr_lstsq) HQR_ERR_SINGULAR in *status.  Returns HQR_ERR_TIMEOUT if the
  * stream is still busy after the wait. */

@@ -14,10 +14,12 @@ PyTorch supplies device memory and streams only.
 """
 from . import _lib
 from ._lib import (BINARY, CHAIN, FIBONACCI, FLAT, GREEDY, OPS, Exec, HQRError, Params, apply_workspace_size,
-                   dag_stats, elimlist, make_exec, make_params, release_plans, validate, version, workspace_size)
+                   dag_stats, elimlist, lstsq_workspace_size, make_exec, make_params, release_plans, validate, version,
+                   workspace_size)
 
 __all__ = ["FLAT", "BINARY", "GREEDY", "FIBONACCI", "CHAIN", "OPS", "Params", "Exec", "HQRError", "make_params",
-           "make_exec", "elimlist", "validate", "dag_stats", "workspace_size", "apply_workspace_size", "factor",
+           "make_exec", "elimlist", "validate", "dag_stats", "workspace_size", "apply_workspace_size",
+           "lstsq_workspace_size", "factor",
            "apply_qt", "apply_q", "lstsq", "colmajor", "r_of", "Workspace", "ApplyWorkspace", "status",
            "release_plans", "version"]
 
@@ -28,12 +30,13 @@ def colmajor(t):
 
 
 class Workspace:
-    """Device workspace for :func:`factor` (a torch uint8 buffer)."""
+    """Device workspace for :func:`factor` (a torch uint8 buffer); with
+    ``nrhs`` > 0 the larger one of :func:`lstsq`."""
 
-    def __init__(self, M, N, params, device="cuda"):
+    def __init__(self, M, N, params, device="cuda", nrhs=0):
         import torch
 
-        self.bytes = workspace_size(M, N, params)
+        self.bytes = lstsq_workspace_size(M, N, nrhs, params) if nrhs > 0 else workspace_size(M, N, params)
         self.buf = torch.empty(self.bytes, dtype=torch.uint8, device=device)
 
     @property
@@ -42,7 +45,7 @@ class Workspace:
 
 
 class ApplyWorkspace:
-    """Device workspace for :func:`apply_qt`, :func:`apply_q` and :func:`lstsq`."""
+    """Device workspace for :func:`apply_qt` and :func:`apply_q`."""
 
     def __init__(self, M, nrhs, params, device="cuda"):
         import torch
@@ -126,10 +129,11 @@ def apply_q(B, M, N, params, work, exec_=None, bwork=None, stream=None, check=Tr
     return _apply(False, B, M, N, params, work, exec_, bwork, stream, check)
 
 
-def lstsq(A, B, params, exec_=None, work=None, bwork=None, stream=None, check=True):
+def lstsq(A, B, params, exec_=None, work=None, stream=None, check=True):
     """Least squares min ||A X - B|| in place: A (M x N) is overwritten by its
     factorization, B (M x nrhs) by X in its first N rows and the residual
-    components of Q^T B below.  Returns (work, bwork)."""
+    components of Q^T B below.  Returns the workspace (it also holds the
+    factors for :func:`apply_qt`)."""
     import torch
 
     M, N, lda = _colmajor_args(A, "A")
@@ -137,16 +141,13 @@ def lstsq(A, B, params, exec_=None, work=None, bwork=None, stream=None, check=Tr
     if MB != M:
         raise ValueError("B must have M = %d rows" % M)
     if work is None:
-        work = Workspace(M, N, params, device=A.device)
-    if bwork is None:
-        bwork = ApplyWorkspace(M, nrhs, params, device=A.device)
+        work = Workspace(M, N, params, device=A.device, nrhs=nrhs)
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
-    _lib.lstsq_ptr(A.data_ptr(), M, N, lda, B.data_ptr(), ldb, nrhs, params, exec_, work.ptr, work.bytes, bwork.ptr,
-                   bwork.bytes, s.cuda_stream)
+    _lib.lstsq_ptr(A.data_ptr(), M, N, lda, B.data_ptr(), ldb, nrhs, params, exec_, work.ptr, work.bytes,
+                   s.cuda_stream)
     if check:
-        _device_status(work, s, "hqr_lstsq (factorization)")
-        _device_status(bwork, s, "hqr_lstsq")
-    return work, bwork
+        _device_status(work, s, "hqr_lstsq")
+    return work
 
 
 def status(work, stream=None):

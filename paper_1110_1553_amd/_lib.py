@@ -42,7 +42,7 @@ TASK_DTYPE = np.dtype([("op", "u1"), ("chunk", "u1"), ("row", "<u2"), ("killer",
                        ("j", "<u2"), ("pad", "<u2"), ("v", "<u4", (3,))])
 
 EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size", "hqr_factor",
-           "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq",
+           "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size", "hqr_lstsq",
            "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_timeline", "hqr_version")
 
 _lib = None
@@ -74,8 +74,8 @@ def load():
     apply_args = [i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp, i64, i32, vp, ctypes.c_size_t, vp]
     lib.hqr_apply_qt.argtypes = apply_args
     lib.hqr_apply_q.argtypes = apply_args
-    lib.hqr_lstsq.argtypes = [vp, i64, i64, i64, vp, i64, i32, P(Params), P(Exec), vp, ctypes.c_size_t, vp,
-                              ctypes.c_size_t, vp]
+    lib.hqr_lstsq_workspace_size.argtypes = [i64, i64, i32, P(Params), P(ctypes.c_size_t)]
+    lib.hqr_lstsq.argtypes = [vp, i64, i64, i64, vp, i64, i32, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
     lib.hqr_status.argtypes = [vp, vp, P(i32)]
     lib.hqr_status_ex.argtypes = [vp, vp, ctypes.c_double, P(i32), P(i32)]
     lib.hqr_release_plans.argtypes = []
@@ -89,7 +89,8 @@ def load():
     lib.hqr_version.argtypes = []
     lib.hqr_version.restype = ctypes.c_char_p
     for name in ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size",
-                 "hqr_factor", "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq", "hqr_status",
+                 "hqr_factor", "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size",
+                 "hqr_lstsq", "hqr_status",
                  "hqr_status_ex"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -182,11 +183,18 @@ def apply_ptr(trans: bool, M: int, N: int, params: Params, exec_: Exec, dwork: i
     _check("hqr_apply_qt" if trans else "hqr_apply_q", rc)
 
 
+def lstsq_workspace_size(M: int, N: int, nrhs: int, params: Params) -> int:
+    n = ctypes.c_size_t()
+    _check("hqr_lstsq_workspace_size",
+           load().hqr_lstsq_workspace_size(M, N, nrhs, ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
 def lstsq_ptr(dA: int, M: int, N: int, lda: int, dB: int, ldb: int, nrhs: int, params: Params, exec_: Exec,
-              dwork: int, work_bytes: int, bwork: int, bwork_bytes: int, stream: int) -> None:
+              dwork: int, work_bytes: int, stream: int) -> None:
     rc = load().hqr_lstsq(ctypes.c_void_p(dA), M, N, lda, ctypes.c_void_p(dB), ldb, nrhs, ctypes.byref(params),
                           ctypes.byref(exec_) if exec_ is not None else None, ctypes.c_void_p(dwork), work_bytes,
-                          ctypes.c_void_p(bwork), bwork_bytes, ctypes.c_void_p(stream))
+                          ctypes.c_void_p(stream))
     _check("hqr_lstsq", rc)
 
 

@@ -22,12 +22,14 @@ namespace {
 constexpr int64_t kDefaultSpinLimit = 20000000;  // polls of one counter (tens of seconds)
 constexpr int kCtrlWords = 64;                    // cursor, status, spare
 
-// order: 0/1 for factorization plans, 2 + trans for apply plans (nbc = B blocks).
+// order: 0/1 for factorization plans, 2 + trans for apply plans (nbc = B
+// blocks); last_a / nrhs: the active chunks of the factorization (ColumnChunks).
 struct PlanKey {
-  int32_t mt, nt, nb, p, a, low, high, coupling, domino, order, device, nbc;
+  int32_t mt, nt, nb, p, a, low, high, coupling, domino, order, device, nbc, last_a, nrhs;
   bool operator<(const PlanKey& o) const {
-    return std::tie(mt, nt, nb, p, a, low, high, coupling, domino, order, device, nbc) <
-           std::tie(o.mt, o.nt, o.nb, o.p, o.a, o.low, o.high, o.coupling, o.domino, o.order, o.device, o.nbc);
+    return std::tie(mt, nt, nb, p, a, low, high, coupling, domino, order, device, nbc, last_a, nrhs) <
+           std::tie(o.mt, o.nt, o.nb, o.p, o.a, o.low, o.high, o.coupling, o.domino, o.order, o.device, o.nbc,
+                    o.last_a, o.nrhs);
   }
 };
 
@@ -82,35 +84,39 @@ int chunks_for(int nb) { return nb / 64; }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  int32_t mt, nt, chunks;
+  int32_t mt, nt, nrt, chunks, last_a;  // nrt: tile columns of right-hand sides (hqr_lstsq)
   size_t ctrl, cnt, tg, tk, tiles, total;
 };
 
 // Workspace: control words, dependency counters, the T factors of the panel
 // kernels (one nb x 16 block column per tile and kind) and the
-// tile-contiguous copy of the matrix the factorization works on.
-Layout layout_for(int64_t M, int64_t N, const hqr_params& p) {
+// tile-contiguous copy of the matrix the factorization works on, followed
+// (hqr_lstsq) by nrhs right-hand-side columns as further tile columns.
+Layout layout_for(int64_t M, int64_t N, const hqr_params& p, int64_t nrhs = 0) {
   Layout L{};
   L.mt = (int32_t)((M + p.nb - 1) / p.nb);
   L.nt = (int32_t)((N + p.nb - 1) / p.nb);
+  L.nrt = (int32_t)((nrhs + p.nb - 1) / p.nb);
   L.chunks = chunks_for(p.nb);
-  const size_t tiles = (size_t)L.mt * L.nt;
+  L.last_a = (int32_t)((N - (int64_t)(L.nt - 1) * p.nb + 63) / 64);
+  const size_t tiles = (size_t)L.mt * L.nt, all = (size_t)L.mt * (L.nt + L.nrt);
   size_t off = 0;
   L.ctrl = off; off = align256(off + kCtrlWords * sizeof(int32_t));
-  L.cnt = off; off = align256(off + tiles * L.chunks * sizeof(int32_t));
+  L.cnt = off; off = align256(off + all * L.chunks * sizeof(int32_t));
   L.tg = off; off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
   L.tk = off; off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
-  L.tiles = off; off = align256(off + tiles * (size_t)p.nb * p.nb * sizeof(double));
+  L.tiles = off; off = align256(off + all * (size_t)p.nb * p.nb * sizeof(double));
   L.total = off;
   return L;
 }
 
 // Cached device plan: order 0/1 = factorization, 2 + trans = apply on nbc
 // blocks of B.
-int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan** out, int32_t nbc = 0) {
+int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan** out, int32_t nbc = 0,
+             const ColumnChunks& cc = ColumnChunks()) {
   int dev = 0;
   if (int rc = record_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
-  PlanKey key{mt, nt, p.nb, p.p, p.a, p.low, p.high, p.coupling, p.domino, order, dev, nbc};
+  PlanKey key{mt, nt, p.nb, p.p, p.a, p.low, p.high, p.coupling, p.domino, order, dev, nbc, cc.last_a, cc.nrhs_cols};
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {
@@ -119,7 +125,7 @@ int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan*
   }
   std::unique_ptr<DevicePlan> dp(new DevicePlan());
   int rc = order >= 2 ? build_apply_plan(mt, nt, nbc, p, order - 2, dp->plan)
-                      : build_plan(mt, nt, p, order, chunks_for(p.nb), dp->plan);
+                      : build_plan(mt, nt, p, order, chunks_for(p.nb), dp->plan, cc);
   if (rc) return rc;
   const size_t bytes = dp->plan.dev.size() * sizeof(DevTask);
   if (bytes) {
@@ -212,6 +218,49 @@ int check_apply_args(int64_t M, int64_t N, const hqr_params* params, const void*
   return 0;
 }
 
+// One factorization launch: copy A (and the nrhs right-hand sides B, which
+// are transformed by Q^T as further tile columns) into the workspace's
+// tiles, run every task of the plan, copy A back when copy_a_out.  The
+// caller has checked the arguments.
+int run_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& p, const hqr_exec& ex, void* dwork,
+               double* dB, int64_t ldb, int32_t nrhs, void* stream, bool copy_a_out) {
+  const Layout L = layout_for(M, N, p, nrhs);
+  ColumnChunks cc;
+  cc.last_a = L.last_a;
+  cc.nrhs_cols = nrhs;
+  DevicePlan* dp = nullptr;
+  int rc = get_plan(L.mt, L.nt, p, ex.order, &dp, 0, cc);
+  if (rc) return rc;
+  char* w = (char*)dwork;
+  LaunchArgs a{};
+  a.ctrl = (int32_t*)(w + L.ctrl);
+  a.cnt = (int32_t*)(w + L.cnt);
+  a.Tg = (double*)(w + L.tg);
+  a.Tk = (double*)(w + L.tk);
+  a.tasks = dp->d_tasks;
+  a.ntasks = (int64_t)dp->plan.dev.size();
+  a.spin_limit = ex.spin_limit > 0 ? ex.spin_limit : kDefaultSpinLimit;
+  a.trace = trace_buffer();
+  a.timeline = timeline_buffer(a.ntasks);
+  if (a.trace) std::memset(a.trace, 0, 2 * kTraceSlots * sizeof(int32_t));
+  a.mt = L.mt;
+  a.nt = L.nt;
+  a.chunks = L.chunks;
+  a.cnt_cols = L.nt + L.nrt;
+  a.B = nullptr;
+  a.A = (double*)(w + L.tiles);
+  a.lda = p.nb;
+  if ((rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, p.nb, L.mt, L.nt, true, stream))) return rc;
+  double* Bt = a.A + (size_t)L.mt * L.nt * p.nb * p.nb;
+  if (nrhs > 0 && (rc = launch_tile_copy(dB, ldb, Bt, M, nrhs, p.nb, p.nb, L.mt, L.nrt, true, stream))) return rc;
+  const int64_t nwords = (int64_t)((L.tg - L.ctrl) / sizeof(int32_t));  // ctrl + counters
+  if ((rc = launch_zero_i32(a.ctrl, nwords, stream))) return rc;
+  int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb);
+  if ((rc = launch_persistent(p.nb, a, workers, stream))) return rc;
+  if (copy_a_out && (rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, p.nb, L.mt, L.nt, false, stream))) return rc;
+  return 0;
+}
+
 }  // namespace
 }  // namespace hqr
 
@@ -296,43 +345,13 @@ int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* 
   if (lda < M) return -4;
   if (!params || check_params(*params)) return -5;
   if (!dwork) return -7;
-  const hqr_params& p = *params;
-  const Layout L = layout_for(M, N, p);
+  const Layout L = layout_for(M, N, *params);
   if (L.mt > 65535 || L.nt > 65535) return -2;
   if (work_bytes < L.total) return -8;
   hqr_exec ex{0, 0, 0};
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -6;
-  DevicePlan* dp = nullptr;
-  int rc = get_plan(L.mt, L.nt, p, ex.order, &dp);
-  if (rc) return rc;
-
-  char* w = (char*)dwork;
-  LaunchArgs a{};
-  a.ctrl = (int32_t*)(w + L.ctrl);
-  a.cnt = (int32_t*)(w + L.cnt);
-  a.Tg = (double*)(w + L.tg);
-  a.Tk = (double*)(w + L.tk);
-  a.tasks = dp->d_tasks;
-  a.ntasks = (int64_t)dp->plan.dev.size();
-  a.spin_limit = ex.spin_limit > 0 ? ex.spin_limit : kDefaultSpinLimit;
-  a.trace = trace_buffer();
-  a.timeline = timeline_buffer(a.ntasks);
-  if (a.trace) std::memset(a.trace, 0, 2 * kTraceSlots * sizeof(int32_t));
-  a.mt = L.mt;
-  a.nt = L.nt;
-  a.chunks = L.chunks;
-  a.cnt_cols = L.nt;
-  a.B = nullptr;
-  a.A = (double*)(w + L.tiles);
-  a.lda = p.nb;
-  if ((rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, p.nb, L.mt, L.nt, true, stream))) return rc;
-  const int64_t nwords = (int64_t)((L.tg - L.ctrl) / sizeof(int32_t));  // ctrl + counters
-  if ((rc = launch_zero_i32(a.ctrl, nwords, stream))) return rc;
-  int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb);
-  if ((rc = launch_persistent(p.nb, a, workers, stream))) return rc;
-  if ((rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, p.nb, L.mt, L.nt, false, stream))) return rc;
-  return 0;
+  return run_factor(dA, M, N, lda, *params, ex, dwork, nullptr, 0, 0, stream, true);
 }
 
 int hqr_apply_workspace_size(int64_t M, int32_t nrhs, const hqr_params* params, size_t* bytes) {
@@ -358,9 +377,18 @@ int hqr_apply_q(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* 
   return run_apply(0, M, N, *params, exec, dwork, work_bytes, dB, ldb, nrhs, bwork, bwork_bytes, stream, true);
 }
 
+int hqr_lstsq_workspace_size(int64_t M, int64_t N, int32_t nrhs, const hqr_params* params, size_t* bytes) {
+  if (M < 1 || M < N) return -1;
+  if (N < 1) return -2;
+  if (nrhs < 1) return -3;
+  if (!params || check_params(*params)) return -4;
+  if (!bytes) return -5;
+  *bytes = layout_for(M, N, *params, nrhs).total;
+  return 0;
+}
+
 int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t ldb, int32_t nrhs,
-              const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* bwork,
-              size_t bwork_bytes, void* stream) {
+              const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream) {
   if (!dA) return -1;
   if (M < 1 || M < N) return -2;
   if (N < 1) return -3;
@@ -370,22 +398,23 @@ int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t
   if (nrhs < 1) return -7;
   if (!params || check_params(*params)) return -8;
   if (!dwork) return -10;
-  if (!bwork) return -12;
-  int rc = hqr_factor(dA, M, N, lda, params, exec, dwork, work_bytes, stream);
-  if (rc) return rc > 0 ? rc : (rc == -7 ? -10 : rc == -8 ? -11 : rc);
   const hqr_params& p = *params;
-  rc = run_apply(1, M, N, p, exec, dwork, work_bytes, dB, ldb, nrhs, bwork, bwork_bytes, stream, false);
-  if (rc) return rc > 0 ? rc : (rc == -12 ? -13 : rc);
-  const Layout L = layout_for(M, N, p);
-  const ApplyLayout AL = apply_layout_for(M, nrhs, p);
-  const char* w = (const char*)dwork;
-  char* bw = (char*)bwork;
-  double* blocks = (double*)(bw + AL.blocks);
-  const int groups = (int)std::min<int64_t>(4, (nrhs + 15) / 16);
-  if ((rc = launch_trsm(p.nb, (const double*)(w + L.tiles), blocks, (int32_t*)(bw + AL.ctrl), N, L.mt, L.nt, AL.nbc,
-                        AL.nbc > 1 ? 4 : groups, stream)))
+  const Layout L = layout_for(M, N, p, nrhs);
+  if (L.mt > 65535 || L.nt + L.nrt > 65535) return -2;
+  if (work_bytes < L.total) return -11;
+  hqr_exec ex{0, 0, 0};
+  if (exec) ex = *exec;
+  if (ex.order != 0 && ex.order != 1) return -9;
+  int rc = run_factor(dA, M, N, lda, p, ex, dwork, dB, ldb, nrhs, stream, true);
+  if (rc) return rc;
+  char* w = (char*)dwork;
+  const double* tiles = (const double*)(w + L.tiles);
+  double* Bt = (double*)(w + L.tiles) + (size_t)L.mt * L.nt * p.nb * p.nb;
+  const int nbc = (nrhs + 63) / 64;
+  const int groups = nbc > 1 ? 4 : (nrhs + 15) / 16;
+  if ((rc = launch_trsm(p.nb, tiles, Bt, L.chunks, (int32_t*)(w + L.ctrl), N, L.mt, L.nt, nbc, groups, stream)))
     return rc;
-  return launch_tile_copy(dB, ldb, blocks, M, nrhs, p.nb, 64, AL.mt, AL.nbc, false, stream);
+  return launch_tile_copy(dB, ldb, Bt, M, nrhs, p.nb, p.nb, L.mt, L.nrt, false, stream);
 }
 
 int hqr_status(const void* dwork, void* stream, int32_t* status) {

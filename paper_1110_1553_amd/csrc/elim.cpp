@@ -252,7 +252,8 @@ std::string validate_elimlist(int32_t mt, int32_t nt, const Elim* list, int64_t 
   return std::string();
 }
 
-std::vector<Task> expand_tasks(int32_t mt, int32_t nt, const std::vector<Elim>& list) {
+std::vector<Task> expand_tasks(int32_t mt, int32_t nt, const std::vector<Elim>& list, int32_t ncols) {
+  if (ncols < nt) ncols = nt;
   std::vector<Task> tasks;
   const int32_t K = std::min(mt, nt);
   std::vector<uint8_t> ts_victim(mt);
@@ -266,13 +267,13 @@ std::vector<Task> expand_tasks(int32_t mt, int32_t nt, const std::vector<Elim>& 
     for (int32_t r = k; r < mt; ++r) {
       if (ts_victim[r]) continue;
       tasks.push_back({GEQRT, r, -1, k, -1});
-      for (int32_t j = k + 1; j < nt; ++j) tasks.push_back({UNMQR, r, -1, k, j});
+      for (int32_t j = k + 1; j < ncols; ++j) tasks.push_back({UNMQR, r, -1, k, j});
     }
     for (size_t q = n; q < end; ++q) {
       const Elim& e = list[q];
       const bool ts = e.kind == HQR_KIND_TS;
       tasks.push_back({(uint8_t)(ts ? TSQRT : TTQRT), e.victim, e.killer, k, -1});
-      for (int32_t j = k + 1; j < nt; ++j) tasks.push_back({(uint8_t)(ts ? TSMQR : TTMQR), e.victim, e.killer, k, j});
+      for (int32_t j = k + 1; j < ncols; ++j) tasks.push_back({(uint8_t)(ts ? TSMQR : TTMQR), e.victim, e.killer, k, j});
     }
     n = end;
   }
@@ -291,7 +292,8 @@ std::vector<Task> expand_tasks(int32_t mt, int32_t nt, const std::vector<Elim>& 
 // task therefore waits until every counter it touches has reached the number
 // of earlier writes in program order, and bumps the counters it writes when
 // done.
-int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chunks, Plan& plan) {
+int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chunks, Plan& plan,
+               const ColumnChunks& ccfg) {
   plan = Plan();
   plan.mt = mt;
   plan.nt = nt;
@@ -302,7 +304,13 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
     std::string why = validate_elimlist(mt, nt, plan.list.data(), (int64_t)plan.list.size());
     if (!why.empty()) return HQR_ERR_INTERNAL;
   }
-  const std::vector<Task> tasks = expand_tasks(mt, nt, plan.list);
+  // tile columns of the launch and their active chunks
+  const int32_t nrt = (ccfg.nrhs_cols + prm.nb - 1) / prm.nb;  // right-hand-side tile columns
+  const int32_t ncols = nt + nrt;
+  std::vector<int32_t> active(ncols, chunks);
+  if (ccfg.last_a > 0 && ccfg.last_a < chunks) active[nt - 1] = ccfg.last_a;
+  if (nrt > 0) active[ncols - 1] = ((ccfg.nrhs_cols - (nrt - 1) * prm.nb) + 63) / 64;
+  const std::vector<Task> tasks = expand_tasks(mt, nt, plan.list, ncols);
   hqr_dag_info& info = plan.info;
   info.eliminations = (int64_t)plan.list.size();
   info.tasks = (int64_t)tasks.size();
@@ -311,14 +319,14 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
     info.weight += op_weight(t.op);
   }
 
-  const size_t ntiles = (size_t)mt * nt;
+  const size_t ntiles = (size_t)mt * ncols;
   std::vector<uint32_t> writes(ntiles, 0);
   std::vector<int64_t> last_writer(ntiles * chunks, -1);
   std::vector<DevTask> dev;
   std::vector<int64_t> wt;  // integer weight of each device task, units of b^3/(3 chunks)
   std::vector<int64_t> pred_off{0}, preds;
   dev.reserve(tasks.size() * chunks);
-  auto tile = [&](int32_t r, int32_t c) { return (size_t)r * nt + c; };
+  auto tile = [&](int32_t r, int32_t c) { return (size_t)r * ncols + c; };
   auto add_pred = [&](int64_t p) {
     if (p < 0) return;
     for (int64_t q = pred_off.back(); q < (int64_t)preds.size(); ++q)
@@ -332,27 +340,29 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
       d.op = t.op;
       d.k = (uint16_t)t.k;
       d.j = (uint16_t)t.k;
+      const int ca = active[t.k];
+      d.chunk = (uint8_t)ca;
       const int64_t id = (int64_t)dev.size();
       if (t.op == GEQRT) {
         d.row = d.killer = (uint16_t)t.row;
         const size_t x = tile(t.row, t.k);
         d.v[0] = writes[x];
-        for (int c = 0; c < chunks; ++c) add_pred(last_writer[x * chunks + c]);
+        for (int c = 0; c < ca; ++c) add_pred(last_writer[x * chunks + c]);
         writes[x]++;
-        for (int c = 0; c < chunks; ++c) last_writer[x * chunks + c] = id;
+        for (int c = 0; c < ca; ++c) last_writer[x * chunks + c] = id;
       } else {
         d.row = (uint16_t)t.row;
         d.killer = (uint16_t)t.killer;
         const size_t xp = tile(t.killer, t.k), xi = tile(t.row, t.k);
         d.v[0] = writes[xp];
         d.v[1] = writes[xi];
-        for (int c = 0; c < chunks; ++c) {
+        for (int c = 0; c < ca; ++c) {
           add_pred(last_writer[xp * chunks + c]);
           add_pred(last_writer[xi * chunks + c]);
         }
         writes[xp]++;
         writes[xi]++;
-        for (int c = 0; c < chunks; ++c) last_writer[xp * chunks + c] = last_writer[xi * chunks + c] = id;
+        for (int c = 0; c < ca; ++c) last_writer[xp * chunks + c] = last_writer[xi * chunks + c] = id;
       }
       dev.push_back(d);
       wt.push_back((int64_t)op_weight(t.op) * chunks);
@@ -361,7 +371,7 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
       // update: read tile (row,k) [UNMQR] or (victim,k) [TS/TT]; write (killer,j) and (row,j)
       const size_t xv = tile(t.row, t.k), xi = tile(t.row, t.j);
       const size_t xp = (t.op == UNMQR) ? 0 : tile(t.killer, t.j);
-      for (int c = 0; c < chunks; ++c) {
+      for (int c = 0; c < active[t.j]; ++c) {
         DevTask d{};
         d.op = t.op;
         d.chunk = (uint8_t)c;

@@ -52,8 +52,10 @@ struct Task {
 
 // Kernel tasks of a list in program order: per panel, first GEQRT(r,k) and
 // UNMQR(r,k,j>k) for every row r >= k that is not a TS victim, then each
-// elimination as TSQRT+TSMQR or TTQRT+TTMQR over j > k.
-std::vector<Task> expand_tasks(int32_t mt, int32_t nt, const std::vector<Elim>& list);
+// elimination as TSQRT+TSMQR or TTQRT+TTMQR over j > k.  The updates run
+// over ncols >= nt tile columns (columns nt.. hold right-hand sides that are
+// transformed but not factored); ncols < 0 means nt.
+std::vector<Task> expand_tasks(int32_t mt, int32_t nt, const std::vector<Elim>& list, int32_t ncols = -1);
 
 // Device task record (24 bytes).  The persistent kernel waits until the
 // dependency counters of the tiles it touches reach v[0..2] and bumps the
@@ -77,9 +79,22 @@ struct Plan {
   hqr_dag_info info{};
 };
 
+// Active column chunks of the tile columns of a launch: the factored
+// columns 0..nt-1 (the last one `last_a` chunks wide: chunks that hold only
+// zero padding are never touched) and `nrhs_cols` right-hand-side columns
+// appended as further tile columns (B is transformed with the matrix and
+// never factored).
+struct ColumnChunks {
+  int32_t last_a = 0;     // 0: every chunk
+  int32_t nrhs_cols = 0;  // right-hand-side columns (0: none)
+};
+
 // Builds the device plan.  `order` 0 = critical-path priority order, 1 =
-// program order.  `chunks` = column chunks per update task.
-int build_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, int chunks, Plan& plan);
+// program order.  `chunks` = column chunks per update task.  A panel task's
+// `chunk` field holds the number of active chunks of its tile column: the
+// counters it waits on and bumps.
+int build_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, int chunks, Plan& plan,
+               const ColumnChunks& cc = ColumnChunks());
 
 // Device plan of B <- Q^T B (trans = 1) or B <- Q B (trans = 0) for the
 // factorization of an mt x nt tile grid, on a B of mt tile rows and `nbc`

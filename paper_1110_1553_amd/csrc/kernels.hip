@@ -647,7 +647,7 @@ __device__ __noinline__ int wait_task(const LaunchArgs& a, int t, const DevTask&
   Smem<NB>& sm = smem<NB>();
   if (threadIdx.x == 0) {
     const int op = task.op, ch = task.chunk, i = task.row, piv = task.killer, k = task.k, j = task.j;
-    const int C = a.chunks;
+    const int C = task.chunk;  // panel tasks: active chunks of the tile column
     int64_t spins = 0;
     bool ok = true;
     switch (op) {
@@ -691,7 +691,7 @@ __device__ __noinline__ void finish_task(const LaunchArgs& a, int t, const DevTa
     trace(a, t, TR_DONE);
     stamp(a, t, 2);
     const int op = task.op, ch = task.chunk, i = task.row, piv = task.killer, k = task.k, j = task.j;
-    const int C = a.chunks;
+    const int C = task.chunk;  // panel tasks: active chunks of the tile column
     auto bump = [&](int32_t* c) { __hip_atomic_fetch_add(c, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); };
     switch (op) {
       case GEQRT:
@@ -844,23 +844,25 @@ __global__ void tile_copy_kernel(double* A, int64_t lda, double* At, int64_t M, 
 // A zero diagonal entry R_jj is recorded in ctrl (status HQR_ERR_SINGULAR,
 // ctrl[6] = max over such j of N - j).
 template <int NB>
-__global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const double* R, double* Y, int32_t* ctrl, int64_t N,
-                                                           int mt, int nt, int i, int groups) {
+__global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const double* R, double* Y, int cpt, int32_t* ctrl,
+                                                           int64_t N, int mt, int nt, int i, int groups) {
   double* xs = hqr_lds;  // x_j or z of this tile row: NB rows x 16 columns, stride 17 (dynamic LDS)
   const int r = threadIdx.x;
   const int blk = blockIdx.x / groups, grp = blockIdx.x % groups;
   const int64_t row0 = (int64_t)i * NB;
   const int nv = (int)((N - row0) < NB ? (N - row0) : NB);  // rows of this tile row inside N
-  double* Yb = Y + ((int64_t)blk * mt) * NB * 64 + 16 * grp * NB;  // column 16 grp of block blk
+  // Y: tile columns of 64 cpt columns; block blk = chunk blk % cpt of tile column blk / cpt
+  const int64_t rstride = (int64_t)NB * 64 * cpt;  // from one tile row of Y to the next
+  double* Yb = Y + (int64_t)(blk / cpt) * mt * rstride + (int64_t)(64 * (blk % cpt) + 16 * grp) * NB;
   double z[16];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) z[c] = Yb[(int64_t)i * NB * 64 + r + (int64_t)c * NB];
+  for (int c = 0; c < 16; ++c) z[c] = Yb[(int64_t)i * rstride + r + (int64_t)c * NB];
   for (int j = i + 1; j < nt; ++j) {
     const int64_t jrow0 = (int64_t)j * NB;
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      const double xv = Yb[(int64_t)j * NB * 64 + r + (int64_t)c * NB];
+      const double xv = Yb[(int64_t)j * rstride + r + (int64_t)c * NB];
       xs[r * 17 + c] = (jrow0 + r < N) ? xv : 0.0;
     }
     __syncthreads();
@@ -908,7 +910,7 @@ __global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const double* R, doub
   }
   if (r < nv) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) Yb[(int64_t)i * NB * 64 + r + (int64_t)c * NB] = xs[r * 17 + c];
+    for (int c = 0; c < 16; ++c) Yb[(int64_t)i * rstride + r + (int64_t)c * NB] = xs[r * 17 + c];
   }
 }
 
@@ -944,23 +946,23 @@ int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, i
   return record_hip(hipGetLastError(), "tile_copy_kernel launch");
 }
 
-int launch_trsm(int nb, const double* R, double* Y, int32_t* ctrl, int64_t N, int mt, int nt, int nbc, int groups,
-                void* stream) {
+int launch_trsm(int nb, const double* R, double* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
+                int groups, void* stream) {
   for (int i = nt - 1; i >= 0; --i) {
     const dim3 grid(nbc * groups), block(nb);
     const size_t lds = (size_t)nb * 17 * sizeof(double);
     switch (nb) {
       case 64:
-        hipLaunchKernelGGL(trsm_tile_row_kernel<64>, grid, block, lds, (hipStream_t)stream, R, Y, ctrl, N, mt, nt, i,
-                           groups);
+        hipLaunchKernelGGL(trsm_tile_row_kernel<64>, grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N, mt, nt,
+                           i, groups);
         break;
       case 128:
-        hipLaunchKernelGGL(trsm_tile_row_kernel<128>, grid, block, lds, (hipStream_t)stream, R, Y, ctrl, N, mt, nt, i,
-                           groups);
+        hipLaunchKernelGGL(trsm_tile_row_kernel<128>, grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N, mt,
+                           nt, i, groups);
         break;
       default:
-        hipLaunchKernelGGL(trsm_tile_row_kernel<256>, grid, block, lds, (hipStream_t)stream, R, Y, ctrl, N, mt, nt, i,
-                           groups);
+        hipLaunchKernelGGL(trsm_tile_row_kernel<256>, grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N, mt,
+                           nt, i, groups);
         break;
     }
     if (int rc = record_hip(hipGetLastError(), "trsm_tile_row_kernel launch")) return rc;

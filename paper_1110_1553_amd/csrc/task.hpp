@@ -47,10 +47,11 @@ int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, i
                      bool in, void* stream);
 
 // Back substitution with the leading N x N triangle of the factored tiles R
-// on the first N rows of Y (blocks of nb x 64, nbc of them; `groups` groups
-// of 16 columns per block are solved), tile row by tile row.
-int launch_trsm(int nb, const double* R, double* Y, int32_t* ctrl, int64_t N, int mt, int nt, int nbc, int groups,
-                void* stream);
+// on the first N rows of Y (tile columns of nb rows x 64 cpt columns; nbc
+// blocks of 64 columns, `groups` groups of 16 columns per block solved),
+// tile row by tile row.
+int launch_trsm(int nb, const double* R, double* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
+                int groups, void* stream);
 
 // Stores "where: message" of a failed HIP call for hqr_last_error(); returns
 // HQR_ERR_HIP on failure, 0 on success.

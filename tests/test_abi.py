@@ -81,8 +81,11 @@ def test_apply_and_lstsq_argument_checks(hqr_lib):
         assert fn(*args(256, 128, 256, 0, need, bneed)) == -10      # nrhs < 1
         assert fn(*args(256, 128, 256, 3, need - 1, bneed)) == -7   # factorization workspace too small
         assert fn(*args(256, 128, 256, 3, need, bneed - 1)) == -12  # apply workspace too small
+    lneed = h.lstsq_workspace_size(256, 128, 3, p)
+    assert lneed >= need + 256 * 64 * 8
     L = hqr_lib.hqr_lstsq
-    assert L(vp(16), 256, 128, 256, vp(16), 200, 1, ctypes.byref(p), None, vp(16), need, vp(16), bneed, None) == -6
-    assert L(vp(16), 256, 128, 256, vp(16), 256, 1, ctypes.byref(p), None, vp(16), need - 1, vp(16), bneed, None) == -11
+    assert L(vp(16), 256, 128, 256, vp(16), 200, 1, ctypes.byref(p), None, vp(16), lneed, None) == -6
+    assert L(vp(16), 256, 128, 256, vp(16), 256, 3, ctypes.byref(p), None, vp(16), lneed - 1, None) == -11
+    assert L(vp(16), 256, 128, 256, vp(16), 256, 0, ctypes.byref(p), None, vp(16), lneed, None) == -7
     with pytest.raises(h.HQRError):
         h.apply_workspace_size(256, 0, p)

@@ -97,6 +97,8 @@ def test_apply_qt_q_lstsq(cuda, tag, M, N, nrhs, prm):
 
     dA2, dB2 = dev(A), dev(B)
     h.lstsq(dA2, dB2, params, ex)
+    # the factorization inside hqr_lstsq is the same launch with B appended
+    assert np.array_equal(np.triu(dA2[:N, :N].cpu().numpy()), R)
     X = dB2.cpu().numpy()[:N]
     Xref = oq.lstsq(A, B)
     e_x = np.linalg.norm(X - Xref) / np.linalg.norm(Xref)
