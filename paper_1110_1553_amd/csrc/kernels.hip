@@ -64,8 +64,8 @@ __device__ __forceinline__ void st4(double* p, d4 v) {
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
@@ -348,8 +348,9 @@ __device__ __forceinline__ double readlane(double v, int lane) {
 // barrier per column.  Leaves V_p in sm.V[0] (with the structure of the
 // kind), T_p in sm.T[0] and in `T`, and the factored columns in A (and R).
 template <int NB, int KIND>
-__device__ __noinline__ void panel_columns(double* A, double* R, double* T, int p) {
+__device__ __forceinline__ void panel_columns(double* A, double* R, double* T, int p) {
   constexpr int NM = NB / 16;  // row slots per thread
+  p = __builtin_amdgcn_readfirstlane(p);  // uniform: row-slot guards become scalar branches
   Smem<NB>& sm = smem<NB>();
   const int tid = threadIdx.x;
   const int cc = tid >> 4;  // panel column of this thread
@@ -495,7 +496,9 @@ __device__ __noinline__ void panel_columns(double* A, double* R, double* T, int 
 // Applies panel p (V_p, T_p staged in sm.V[0], sm.T[0]) to the strips
 // p+1 .. s_last of the tile(s) (at most 3): wave w takes strip p + 1 + w.
 template <int NB, int KIND>
-__device__ __noinline__ void panel_strips(double* A, double* R, int p, int s_last) {
+__device__ __forceinline__ void panel_strips(double* A, double* R, int p, int s_last) {
+  p = __builtin_amdgcn_readfirstlane(p);
+  s_last = __builtin_amdgcn_readfirstlane(s_last);
   Smem<NB>& sm = smem<NB>();
   const Lane L;
   const int s = p + 1 + L.wave;
@@ -514,8 +517,9 @@ __device__ __noinline__ void panel_strips(double* A, double* R, int p, int s_las
 // T from `T`) to the columns right of the block, 64 at a time: wave w holds
 // strip 4c + w of chunk c in registers across the four panels.
 template <int NB, int KIND>
-__device__ __noinline__ void panel_block_update(double* A, double* R, const double* T, int b) {
+__device__ __forceinline__ void panel_block_update(double* A, double* R, const double* T, int b) {
   constexpr int NRB = NB / 16;
+  b = __builtin_amdgcn_readfirstlane(b);
   Smem<NB>& sm = smem<NB>();
   const Lane L;
   const int p0 = 4 * b;
@@ -768,7 +772,7 @@ __device__ __noinline__ void apply_task(const LaunchArgs& a, const DevTask& task
 // Every task a workgroup waits for was taken earlier by a running
 // workgroup, so the wait always ends.
 template <int NB>
-__global__ __launch_bounds__(NT, 2) void persistent_kernel(LaunchArgs a) {
+__global__ __launch_bounds__(NT, 1) void persistent_kernel(LaunchArgs a) {
   for (;;) {
     const int t = take_task<NB>(a);
     if (t < 0) break;
