@@ -79,7 +79,10 @@ int32_t* trace_buffer() {
 }
 std::map<PlanKey, std::unique_ptr<DevicePlan>> g_plans;
 
-int chunks_for(int nb) { return nb / 64; }
+// Columns per update task: one 16-column strip per wave of the persistent
+// workgroup (8 waves), at most the tile.
+int chunk_cols(int nb) { return nb < 128 ? nb : 128; }
+int chunks_for(int nb) { return nb / chunk_cols(nb); }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -98,7 +101,8 @@ Layout layout_for(int64_t M, int64_t N, const hqr_params& p, int64_t nrhs = 0) {
   L.nt = (int32_t)((N + p.nb - 1) / p.nb);
   L.nrt = (int32_t)((nrhs + p.nb - 1) / p.nb);
   L.chunks = chunks_for(p.nb);
-  L.last_a = (int32_t)((N - (int64_t)(L.nt - 1) * p.nb + 63) / 64);
+  const int cw = chunk_cols(p.nb);
+  L.last_a = (int32_t)((N - (int64_t)(L.nt - 1) * p.nb + cw - 1) / cw);
   const size_t tiles = (size_t)L.mt * L.nt, all = (size_t)L.mt * (L.nt + L.nrt);
   size_t off = 0;
   L.ctrl = off; off = align256(off + kCtrlWords * sizeof(int32_t));
@@ -412,7 +416,8 @@ int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t
   double* Bt = (double*)(w + L.tiles) + (size_t)L.mt * L.nt * p.nb * p.nb;
   const int nbc = (nrhs + 63) / 64;
   const int groups = nbc > 1 ? 4 : (nrhs + 15) / 16;
-  if ((rc = launch_trsm(p.nb, tiles, Bt, L.chunks, (int32_t*)(w + L.ctrl), N, L.mt, L.nt, nbc, groups, stream)))
+  // the right-hand sides are tile columns of nb: nb / 64 blocks of 64 columns each
+  if ((rc = launch_trsm(p.nb, tiles, Bt, p.nb / 64, (int32_t*)(w + L.ctrl), N, L.mt, L.nt, nbc, groups, stream)))
     return rc;
   return launch_tile_copy(dB, ldb, Bt, M, nrhs, p.nb, p.nb, L.mt, L.nrt, false, stream);
 }

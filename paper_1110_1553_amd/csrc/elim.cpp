@@ -309,7 +309,8 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
   const int32_t ncols = nt + nrt;
   std::vector<int32_t> active(ncols, chunks);
   if (ccfg.last_a > 0 && ccfg.last_a < chunks) active[nt - 1] = ccfg.last_a;
-  if (nrt > 0) active[ncols - 1] = ((ccfg.nrhs_cols - (nrt - 1) * prm.nb) + 63) / 64;
+  const int32_t cw = prm.nb / chunks;  // columns per chunk
+  if (nrt > 0) active[ncols - 1] = ((ccfg.nrhs_cols - (nrt - 1) * prm.nb) + cw - 1) / cw;
   const std::vector<Task> tasks = expand_tasks(mt, nt, plan.list, ncols);
   hqr_dag_info& info = plan.info;
   info.eliminations = (int64_t)plan.list.size();

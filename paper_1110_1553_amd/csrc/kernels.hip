@@ -11,11 +11,13 @@
 // a finished factorization one after another with the V panels staged
 // through double-buffered LDS.
 //
-// Work split inside a workgroup (256 threads, 4 waves): every wave owns a
-// strip of 16 matrix columns and keeps the strip (b x 16 doubles) in
-// registers as b/16 MFMA accumulators, so the reduction V^T C over the rows
-// and the update C -= V W stay inside the wave; the waves only share the V
-// panel and T in LDS.
+// Work split inside a workgroup (512 threads, 8 waves, one workgroup per CU
+// so two waves share each SIMD): every wave owns a strip of 16 matrix
+// columns and keeps the strip (b x 16 doubles) in registers as b/16 MFMA
+// accumulators, so the reduction V^T C over the rows and the update
+// C -= V W stay inside the wave; the waves only share the V panel and T in
+// LDS.  An update task covers 128 columns (8 strips).  The column loop of
+// the panel kernels runs on waves 0-3 (16 columns x 16 lanes).
 //
 // Register layout of an accumulator block (16 rows x 16 columns): lane l,
 // element r holds MFMA row (l / 16) + 4 r, column l % 16.  Matrix rows are
@@ -36,7 +38,7 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 
 constexpr int IB = 16;      // inner blocking (columns per panel)
 constexpr int LDV = IB + 1; // LDS row stride of a staged panel (odd: no bank conflicts)
-constexpr int NT = 256;     // threads per workgroup
+constexpr int NT = 512;     // threads per workgroup (8 waves, 2 per SIMD)
 
 enum Kind { K_UNM = 0, K_TS = 1, K_TT = 2 };
 
@@ -44,9 +46,24 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Global-memory accessors.  The tile pointers reach the tile kernels through
+// the task records, where the compiler no longer knows their address space
+// and would emit flat instructions; flat loads also count against the LDS
+// counter, so every wait for an LDS read would wait for them as well.
+#ifndef HQR_GLOBAL_AS
+#define HQR_GLOBAL_AS __attribute__((address_space(1)))
+#endif
+typedef HQR_GLOBAL_AS double gdouble;
+typedef HQR_GLOBAL_AS d2 gd2;
+
+__device__ __forceinline__ double gload(const double* p) { return *(const gdouble*)p; }
+__device__ __forceinline__ void gstore(double* p, double v) { *(gdouble*)p = v; }
+__device__ __forceinline__ d2 gload2(const double* p) { return *(const gd2*)p; }
+__device__ __forceinline__ void gstore2(double* p, d2 v) { *(gd2*)p = v; }
+
 __device__ __forceinline__ d4 ld4(const double* p) {
-  const d2 x = *reinterpret_cast<const d2*>(p);
-  const d2 y = *reinterpret_cast<const d2*>(p + 2);
+  const d2 x = gload2(p);
+  const d2 y = gload2(p + 2);
   d4 r;
   r.x = x.x; r.y = x.y; r.z = y.x; r.w = y.y;
   return r;
@@ -55,8 +72,8 @@ __device__ __forceinline__ d4 ld4(const double* p) {
 __device__ __forceinline__ void st4(double* p, d4 v) {
   d2 x, y;
   x.x = v.x; x.y = v.y; y.x = v.z; y.y = v.w;
-  *reinterpret_cast<d2*>(p) = x;
-  *reinterpret_cast<d2*>(p + 2) = y;
+  gstore2(p, x);
+  gstore2(p + 2, y);
 }
 
 // One DPP step on a double: each lane receives the value of the lane picked
@@ -133,15 +150,24 @@ __device__ __forceinline__ bool row_block_active(int rb, int p) {
 // MFMAs of the current one; scheduling barriers keep the compiler from
 // hoisting all operand loads at once, which would not fit next to the
 // accumulators.  Consecutive MFMAs never write the same accumulator.
-template <int NB, int KIND, bool TRANS = true>
-__device__ __forceinline__ void apply_panel(d4 (&acc)[NB / 16], const double* __restrict__ Vs,
-                                            const double* __restrict__ Ts, int p, double* c1,
-                                            int64_t ldc, const Lane& L) {
+//
+// A wave may hold SPW strips (columns 16 w + 64 s, s < SPW, of the chunk):
+// every V operand read from LDS then feeds SPW products.
+template <int NB, int KIND, bool TRANS, int SPW>
+__device__ __forceinline__ void apply_panel_n(d4 (&acc)[SPW][NB / 16], const double* __restrict__ Vs,
+                                              const double* __restrict__ Ts, int p, double* c1, int64_t ldc,
+                                              const Lane& L) {
   constexpr int NRB = NB / 16;
-  d4 c1v = {0.0, 0.0, 0.0, 0.0};
-  if (KIND != K_UNM) c1v = ld4(c1 + 4 * L.g + (int64_t)L.q * ldc);
-  d4 w0 = {0.0, 0.0, 0.0, 0.0}, w1 = w0;
-  // ---- W = V^T acc: group rb = 4 products, alternating two partial sums
+  d4 c1v[SPW];
+  d4 w0[SPW], w1[SPW];
+#pragma unroll
+  for (int s = 0; s < SPW; ++s) {
+    c1v[s] = d4{0.0, 0.0, 0.0, 0.0};
+    if (KIND != K_UNM) c1v[s] = ld4(c1 + 4 * L.g + (int64_t)(L.q + 64 * s) * ldc);
+    w0[s] = d4{0.0, 0.0, 0.0, 0.0};
+    w1[s] = w0[s];
+  }
+  // ---- W = V^T acc: group rb = 4 products per strip, alternating two partial sums
   {
     const double* va = Vs + 4 * L.g * LDV + L.pq;  // + (16 rb + r) * LDV
     double a[4], an[4];
@@ -162,24 +188,38 @@ __device__ __forceinline__ void apply_panel(d4 (&acc)[NB / 16], const double* __
 #pragma unroll
           for (int r = 0; r < 4; ++r) an[r] = va[(16 * (rb + 1) + r) * LDV];
         }
-        w0 = mfma(a[0], acc[rb][0], w0);
-        w1 = mfma(a[1], acc[rb][1], w1);
-        w0 = mfma(a[2], acc[rb][2], w0);
-        w1 = mfma(a[3], acc[rb][3], w1);
+#pragma unroll
+        for (int s = 0; s < SPW; ++s) {
+          w0[s] = mfma(a[0], acc[s][rb][0], w0[s]);
+          w1[s] = mfma(a[1], acc[s][rb][1], w1[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < SPW; ++s) {
+          w0[s] = mfma(a[2], acc[s][rb][2], w0[s]);
+          w1[s] = mfma(a[3], acc[s][rb][3], w1[s]);
+        }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r] = an[r];
       }
     }
   }
-  d4 w = w0 + w1;
-  if (KIND != K_UNM) w += c1v;
-  d4 w2t = {0.0, 0.0, 0.0, 0.0};
+  d4 wn[SPW];
+  {
+    double t[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-    w2t = mfma(TRANS ? Ts[(4 * L.g + r) * LDV + L.pq] : Ts[L.pq * LDV + 4 * L.g + r], w[r], w2t);
-  if (KIND != K_UNM) st4(c1 + 4 * L.g + (int64_t)L.q * ldc, c1v - w2t);
-  const d4 wn = -w2t;
+    for (int r = 0; r < 4; ++r) t[r] = TRANS ? Ts[(4 * L.g + r) * LDV + L.pq] : Ts[L.pq * LDV + 4 * L.g + r];
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+      d4 w = w0[s] + w1[s];
+      if (KIND != K_UNM) w += c1v[s];
+      d4 w2t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w2t = mfma(t[r], w[r], w2t);
+      if (KIND != K_UNM) st4(c1 + 4 * L.g + (int64_t)(L.q + 64 * s) * ldc, c1v[s] - w2t);
+      wn[s] = -w2t;
+    }
+  }
   // ---- acc -= V W: groups of two row blocks, products interleaved
   {
     const double* vc = Vs + L.pq * LDV + 4 * L.g;  // + 16 rb LDV + r
@@ -197,13 +237,24 @@ __device__ __forceinline__ void apply_panel(d4 (&acc)[NB / 16], const double* __
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          if (act0) acc[rb] = mfma(b0[r], wn[r], acc[rb]);
-          if (act1) acc[rb + 1] = mfma(b1[r], wn[r], acc[rb + 1]);
+#pragma unroll
+          for (int s = 0; s < SPW; ++s) {
+            if (act0) acc[s][rb] = mfma(b0[r], wn[s][r], acc[s][rb]);
+            if (act1) acc[s][rb + 1] = mfma(b1[r], wn[s][r], acc[s][rb + 1]);
+          }
         }
         __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
+}
+
+// One strip per wave.
+template <int NB, int KIND, bool TRANS = true>
+__device__ __forceinline__ void apply_panel(d4 (&acc)[NB / 16], const double* __restrict__ Vs,
+                                            const double* __restrict__ Ts, int p, double* c1, int64_t ldc,
+                                            const Lane& L) {
+  apply_panel_n<NB, KIND, TRANS, 1>(reinterpret_cast<d4 (&)[1][NB / 16]>(acc), Vs, Ts, p, c1, ldc, L);
 }
 
 template <int NB, int KIND>
@@ -232,7 +283,7 @@ __device__ __forceinline__ void store_strip(const d4 (&acc)[NB / 16], double* ba
 // reads are skipped.
 template <int NB>
 struct PanelPrefetch {
-  static constexpr int PER = NB / 32;  // double2 loads per thread
+  static constexpr int PER = NB * 8 / NT;  // double2 loads per thread
   d2 v[PER];
   double t;
 };
@@ -246,9 +297,9 @@ __device__ __forceinline__ void prefetch_panel(PanelPrefetch<NB>& pf, const doub
     const int e = it * NT + tid;
     const int col = e / (NB / 2), row = 2 * (e % (NB / 2));
     const bool needed = (KIND == K_UNM) ? (row >= 16 * p) : (KIND == K_TT ? row < 16 * p + 16 : true);
-    if (needed) pf.v[it] = *reinterpret_cast<const d2*>(V + row + (int64_t)(16 * p + col) * ld);
+    if (needed) pf.v[it] = gload2(V + row + (int64_t)(16 * p + col) * ld);
   }
-  pf.t = Tblk[tid];
+  if (tid < 256) pf.t = gload(Tblk + tid);
 }
 
 template <int NB, int KIND>
@@ -273,7 +324,7 @@ __device__ __forceinline__ void stage_panel(const PanelPrefetch<NB>& pf, double*
       }
     }
   }
-  Ts[(tid & 15) * LDV + (tid >> 4)] = pf.t;
+  if (tid < 256) Ts[(tid & 15) * LDV + (tid >> 4)] = pf.t;
 }
 
 // ---------------------------------------------------------------------------
@@ -283,17 +334,19 @@ __device__ __forceinline__ void stage_panel(const PanelPrefetch<NB>& pf, double*
 //   C1: killer tile (TS/TT).
 // TRANS applies Q^T (the panels in factorization order, T^T); otherwise Q
 // (the panels in reverse order, T).
-template <int NB, int KIND, bool TRANS>
+template <int NB, int KIND, bool TRANS, int CW>
 __device__ __forceinline__ void run_update(Smem<NB>& sm, const double* V, const double* T, double* C1, double* C2,
                                            int64_t ld) {
   constexpr int NP = NB / IB;
   const Lane L;
+  const bool on = 16 * L.wave < CW;  // waves holding a strip of the chunk (uniform per wave)
   d4 acc[NB / 16];
   const int64_t coloff = (int64_t)(16 * L.wave) * ld;
-  load_strip<NB, K_TS>(acc, C2 + coloff, ld, 0, L);
+  if (on) load_strip<NB, K_TS>(acc, C2 + coloff, ld, 0, L);
   PanelPrefetch<NB> pf;
   const int pfirst = TRANS ? 0 : NP - 1;
   prefetch_panel<NB, KIND>(pf, V, ld, T + pfirst * 256, pfirst);
+#pragma unroll 1
   for (int it = 0; it < NP; ++it) {
     const int p = TRANS ? it : NP - 1 - it;
     double* Vs = sm.V[it & 1];
@@ -304,9 +357,9 @@ __device__ __forceinline__ void run_update(Smem<NB>& sm, const double* V, const 
       const int pn = TRANS ? p + 1 : p - 1;
       prefetch_panel<NB, KIND>(pf, V, ld, T + pn * 256, pn);
     }
-    apply_panel<NB, KIND, TRANS>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p, ld, L);
+    if (on) apply_panel<NB, KIND, TRANS>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p, ld, L);
   }
-  store_strip<NB, K_TS>(acc, C2 + coloff, ld, 0, L);
+  if (on) store_strip<NB, K_TS>(acc, C2 + coloff, ld, 0, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -325,11 +378,9 @@ __device__ __forceinline__ void run_update(Smem<NB>& sm, const double* V, const 
 // The tile is processed in blocks of 64 columns (four 16-column panels).
 // Inside a block each panel is factored (panel_columns) and applied to the
 // block's remaining strips (panel_strips); at the end of a block its four
-// panels are applied to the columns right of the block, 64 columns at a
-// time with the strips held in registers across the four panels
-// (panel_block_update), so those columns are read and written once per
-// block instead of once per panel.  The phases are separate functions so
-// each gets its own register allocation.
+// panels are applied to the columns right of the block, one strip per wave
+// held in registers across the four panels (panel_block_update), so those
+// columns are read and written once per block instead of once per panel.
 
 // Reads lane `lane` (wave-uniform) of a double held in VGPRs.
 __device__ __forceinline__ double readlane(double v, int lane) {
@@ -353,8 +404,10 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
   p = __builtin_amdgcn_readfirstlane(p);  // uniform: row-slot guards become scalar branches
   Smem<NB>& sm = smem<NB>();
   const int tid = threadIdx.x;
-  const int cc = tid >> 4;  // panel column of this thread
-  const int q = tid & 15;   // its rows are base + q + 16 m
+  // waves 0-3 hold the panel; waves 4-7 only take part in the barriers
+  const bool ct = tid < 256;
+  const int cc = ct ? tid >> 4 : 16;  // panel column of this thread (16: none)
+  const int q = tid & 15;             // its rows are base + q + 16 m
   const int c0 = 16 * p;
   const int base = (KIND == K_UNM) ? c0 : 0;
   // row slots that can hold rows of the panel (uniform): GEQRT rows < NB,
@@ -370,12 +423,12 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
   for (int m = 0; m < NM; ++m) {
     const int r = base + q + 16 * m;
     // TT: rows below the diagonal hold the tile's own GEQRT reflectors
-    const bool act = m < nm && (KIND != K_TT || r <= c0 + cc);
-    x[m] = act ? col[r] : 0.0;
+    const bool act = ct && m < nm && (KIND != K_TT || r <= c0 + cc);
+    x[m] = act ? gload(col + r) : 0.0;
   }
   double rv = 0.0;  // TS/TT: R(c0 + q, c0 + cc) of the killer's diagonal block
-  if (KIND != K_UNM && q <= cc) rv = R[(c0 + q) + (int64_t)(c0 + cc) * NB];
-  Zs[cc * LDV + q] = 0.0;  // entries (i, j) with i >= j stay zero
+  if (KIND != K_UNM && ct && q <= cc) rv = gload(R + (c0 + q) + (int64_t)(c0 + cc) * NB);
+  if (ct) Zs[cc * LDV + q] = 0.0;  // entries (i, j) with i >= j stay zero
   for (int jj = 0; jj < 16; ++jj) {
     double* vb = Vb + (jj & 1) * NB;
     if (cc == jj) {
@@ -419,7 +472,7 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
       if (q == 0) sm.tau[jj] = tau;
     }
     __syncthreads();
-    if (cc != jj) {
+    if (ct && cc != jj) {
       const double tau = sm.tau[jj];
       double v[NM];
       double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
@@ -470,17 +523,17 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
       Ts[i * LDV + jj] = t[jj];
-      T[p * 256 + i + 16 * jj] = t[jj];
+      gstore(T + p * 256 + i + 16 * jj, t[jj]);
     }
   }
   // ---- the factored panel back to the tiles, and V_p into LDS
 #pragma unroll
   for (int m = 0; m < NM; ++m) {
-    if (m < nm) {
+    if (ct && m < nm) {
       const int r = base + q + 16 * m;
       const bool act = KIND != K_TT || r <= c0 + cc;
       if (act) {
-        col[r] = x[m];
+        gstore(col + r, x[m]);
         double vv = x[m];
         if (KIND == K_UNM && m == 0 && q <= cc) vv = (q == cc) ? 1.0 : 0.0;  // unit diagonal, R above
         Vs[r * LDV + cc] = vv;
@@ -489,7 +542,7 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
       }
     }
   }
-  if (KIND != K_UNM && q <= cc) R[(c0 + q) + (int64_t)(c0 + cc) * NB] = rv;
+  if (KIND != K_UNM && ct && q <= cc) gstore(R + (c0 + q) + (int64_t)(c0 + cc) * NB, rv);
   __syncthreads();
 }
 
@@ -514,8 +567,8 @@ __device__ __forceinline__ void panel_strips(double* A, double* R, int p, int s_
 }
 
 // Applies the four panels of block b (panels 4b .. 4b+3, V from the tile,
-// T from `T`) to the columns right of the block, 64 at a time: wave w holds
-// strip 4c + w of chunk c in registers across the four panels.
+// T from `T`) to the columns right of the block, one 16-column strip per
+// wave held in registers across the four panels.
 template <int NB, int KIND>
 __device__ __forceinline__ void panel_block_update(double* A, double* R, const double* T, int b) {
   constexpr int NRB = NB / 16;
@@ -526,13 +579,15 @@ __device__ __forceinline__ void panel_block_update(double* A, double* R, const d
   // row blocks any of the four panels touches
   const int lo = (KIND == K_UNM) ? p0 : 0;
   const int hi = (KIND == K_TT) ? p0 + 3 : NRB - 1;
-  for (int c = b + 1; c < NB / 64; ++c) {
-    const int s = 4 * c + L.wave;
+  // passes over the strips right of the block, one strip per wave
+  for (int s0 = 4 * (b + 1); s0 < NRB; s0 += NT / 64) {
+    const int s = s0 + L.wave;
+    const bool on = s < NRB;  // uniform per wave
     double* strip = A + (int64_t)(16 * s) * NB;
     d4 acc[NRB];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
-      if (rb >= lo && rb <= hi) acc[rb] = ld4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB);
+      if (on && rb >= lo && rb <= hi) acc[rb] = ld4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB);
     PanelPrefetch<NB> pf;
     prefetch_panel<NB, KIND>(pf, A, NB, T + p0 * 256, p0);
     for (int p = p0; p < p0 + 4; ++p) {
@@ -541,11 +596,12 @@ __device__ __forceinline__ void panel_block_update(double* A, double* R, const d
       stage_panel<NB, KIND>(pf, Vs, Ts, p);
       __syncthreads();
       if (p + 1 < p0 + 4) prefetch_panel<NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
-      apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
+      if (on)
+        apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
     }
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
-      if (rb >= lo && rb <= hi) st4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB, acc[rb]);
+      if (on && rb >= lo && rb <= hi) st4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB, acc[rb]);
     __syncthreads();
   }
 }
@@ -742,13 +798,16 @@ __device__ __noinline__ void panel_task(const LaunchArgs& a, const DevTask& task
   __builtin_amdgcn_s_setprio(0);
 }
 
+// An update task covers one column chunk: 128 columns (one 16-column strip
+// per wave) for tiles of 128 or 256, the whole tile for nb = 64.
 template <int NB, int KIND>
 __device__ __noinline__ void update_task(const LaunchArgs& a, const DevTask& task) {
+  constexpr int CW = NB < 128 ? NB : 128;
   double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
-  const int64_t colchunk = (int64_t)task.chunk * 64 * NB;
-  run_update<NB, KIND, true>(smem<NB>(), tile_ptr(a, NB, task.row, task.k), t_block(T, a, NB, task.row, task.k),
-                             KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.j) + colchunk,
-                             tile_ptr(a, NB, task.row, task.j) + colchunk, NB);
+  const int64_t colchunk = (int64_t)task.chunk * CW * NB;
+  run_update<NB, KIND, true, CW>(smem<NB>(), tile_ptr(a, NB, task.row, task.k), t_block(T, a, NB, task.row, task.k),
+                                 KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.j) + colchunk,
+                                 tile_ptr(a, NB, task.row, task.j) + colchunk, NB);
 }
 
 // Block of 64 columns of B (nb x 64, column-major) of tile row r.
@@ -760,9 +819,9 @@ __device__ __forceinline__ double* b_block(const LaunchArgs& a, int nb, int r, i
 template <int NB, int KIND, bool TRANS>
 __device__ __noinline__ void apply_task(const LaunchArgs& a, const DevTask& task) {
   double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
-  run_update<NB, KIND, TRANS>(smem<NB>(), tile_ptr(a, NB, task.row, task.k), t_block(T, a, NB, task.row, task.k),
-                              KIND == K_UNM ? nullptr : b_block(a, NB, task.killer, task.j),
-                              b_block(a, NB, task.row, task.j), NB);
+  run_update<NB, KIND, TRANS, 64>(smem<NB>(), tile_ptr(a, NB, task.row, task.k), t_block(T, a, NB, task.row, task.k),
+                                 KIND == K_UNM ? nullptr : b_block(a, NB, task.killer, task.j),
+                                 b_block(a, NB, task.row, task.j), NB);
 }
 
 // Persistent scheduler.  Workgroups take task indices from a global cursor

@@ -71,7 +71,7 @@ def test_dag_counts_and_weight_match(hqr_lib):
         assert st["count"] == counts
         assert st["weight"] == el.weight(tasks) == el.weight_formula(mt, nt)
         updates = sum(counts[o] for o in ("UNMQR", "TSMQR", "TTMQR"))
-        assert st["device_tasks"] == len(tasks) + 3 * updates  # 4 column chunks at nb = 256
+        assert st["device_tasks"] == len(tasks) + updates  # 2 column chunks of 128 at nb = 256
 
 
 def test_survey_task_counts(hqr_lib):
