@@ -97,6 +97,15 @@ __device__ __forceinline__ double sum16(double v) {
   return v;
 }
 
+// Workgroup barrier that orders LDS accesses only: global stores still in
+// flight are not waited for (the data they carry is not read by another
+// wave before a full barrier).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int NB>
 struct Smem {
   double V[2][NB * LDV];  // staged V panels (row-major, stride LDV)
@@ -352,7 +361,7 @@ __device__ __forceinline__ void run_update(Smem<NB>& sm, const double* V, const 
     double* Vs = sm.V[it & 1];
     double* Ts = sm.T[it & 1];
     stage_panel<NB, KIND>(pf, Vs, Ts, p);
-    __syncthreads();
+    lds_barrier();
     if (it + 1 < NP) {
       const int pn = TRANS ? p + 1 : p - 1;
       prefetch_panel<NB, KIND>(pf, V, ld, T + pn * 256, pn);
@@ -411,7 +420,8 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
   const int c0 = 16 * p;
   const int base = (KIND == K_UNM) ? c0 : 0;
   // row slots that can hold rows of the panel (uniform): GEQRT rows < NB,
-  // TT rows <= c0 + 15
+  // TT rows <= c0 + 15.  The other slots hold zeros; the column loop runs
+  // over all slots (branch-free), only loads and stores skip them.
   const int nm = (KIND == K_UNM) ? NM - p : (KIND == K_TT ? p + 1 : NM);
   double* Vs = sm.V[0];
   double* Ts = sm.T[0];
@@ -438,14 +448,12 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        if (m < nm) {
-          double t = x[m];
-          if (KIND == K_UNM && m == 0 && q <= jj) t = 0.0;  // rows <= j are not in the tail
-          if ((m & 3) == 0) s0 += t * t;
-          if ((m & 3) == 1) s1 += t * t;
-          if ((m & 3) == 2) s2 += t * t;
-          if ((m & 3) == 3) s3 += t * t;
-        }
+        double t = x[m];
+        if (KIND == K_UNM && m == 0 && q <= jj) t = 0.0;  // rows <= j are not in the tail
+        if ((m & 3) == 0) s0 += t * t;
+        if ((m & 3) == 1) s1 += t * t;
+        if ((m & 3) == 2) s2 += t * t;
+        if ((m & 3) == 3) s3 += t * t;
       }
       const double ss = sum16((s0 + s1) + (s2 + s3));
       double tau = 0.0, beta = alpha, scale = 1.0;
@@ -457,35 +465,30 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
       }
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        if (m < nm) {
-          if (KIND == K_UNM && m == 0) {
-            if (q > jj) x[0] *= scale;
-            if (q == jj) x[0] = beta;
-            vb[q] = (q > jj) ? x[0] : (q == jj ? 1.0 : 0.0);
-          } else {
-            x[m] *= scale;
-            vb[q + 16 * m] = x[m];
-          }
+        if (KIND == K_UNM && m == 0) {
+          if (q > jj) x[0] *= scale;
+          if (q == jj) x[0] = beta;
+          vb[q] = (q > jj) ? x[0] : (q == jj ? 1.0 : 0.0);
+        } else {
+          x[m] *= scale;
+          vb[q + 16 * m] = x[m];
         }
       }
       if (KIND != K_UNM && q == jj) rv = beta;
       if (q == 0) sm.tau[jj] = tau;
     }
-    __syncthreads();
+    lds_barrier();
     if (ct && cc != jj) {
       const double tau = sm.tau[jj];
       double v[NM];
       double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        v[m] = 0.0;
-        if (m < nm) {
-          v[m] = vb[q + 16 * m];
-          if ((m & 3) == 0) d0 += v[m] * x[m];
-          if ((m & 3) == 1) d1 += v[m] * x[m];
-          if ((m & 3) == 2) d2 += v[m] * x[m];
-          if ((m & 3) == 3) d3 += v[m] * x[m];
-        }
+        v[m] = vb[q + 16 * m];
+        if ((m & 3) == 0) d0 += v[m] * x[m];
+        if ((m & 3) == 1) d1 += v[m] * x[m];
+        if ((m & 3) == 2) d2 += v[m] * x[m];
+        if ((m & 3) == 3) d3 += v[m] * x[m];
       }
       // TS/TT: the unit entry of v sits in row j of the triangle on top,
       // where lane q = jj of column c0 + cc holds R(j, c0 + cc)
@@ -495,8 +498,7 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
         if (tau != 0.0) {
           const double f = tau * d;
 #pragma unroll
-          for (int m = 0; m < NM; ++m)
-            if (m < nm) x[m] -= f * v[m];
+          for (int m = 0; m < NM; ++m) x[m] -= f * v[m];
           if (KIND != K_UNM && q == jj) rv -= f;
         }
       } else if (q == 0) {
@@ -504,7 +506,7 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
   // ---- T: T(jj,jj) = tau_jj, T(0:jj, jj) = -tau_jj T(0:jj,0:jj) (V^T v_jj)(0:jj)
   //      (Schreiber-Van Loan forward recurrence, one row of T per lane; the
   //      sums for the later columns are accumulated as each entry appears)
@@ -543,7 +545,9 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
     }
   }
   if (KIND != K_UNM && ct && q <= cc) gstore(R + (c0 + q) + (int64_t)(c0 + cc) * NB, rv);
-  __syncthreads();
+  // V_p and T_p in LDS are what the strips of the block need next; the
+  // columns just stored are read back (block update) only after a full barrier
+  lds_barrier();
 }
 
 // Applies panel p (V_p, T_p staged in sm.V[0], sm.T[0]) to the strips
@@ -594,7 +598,7 @@ __device__ __forceinline__ void panel_block_update(double* A, double* R, const d
       double* Vs = sm.V[p & 1];
       double* Ts = sm.T[p & 1];
       stage_panel<NB, KIND>(pf, Vs, Ts, p);
-      __syncthreads();
+      lds_barrier();
       if (p + 1 < p0 + 4) prefetch_panel<NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
       if (on)
         apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
@@ -611,7 +615,10 @@ __device__ __forceinline__ void run_panel(double* A, double* R, double* T) {
   for (int b = 0; b < NB / 64; ++b) {
     for (int p = 4 * b; p < 4 * b + 4; ++p) {
       panel_columns<NB, KIND>(A, R, T, p);
-      if (p < 4 * b + 3) panel_strips<NB, KIND>(A, R, p, 4 * b + 3);
+      if (p < 4 * b + 3)
+        panel_strips<NB, KIND>(A, R, p, 4 * b + 3);
+      else
+        __syncthreads();  // the block update stages V from the stored columns
     }
     if (b + 1 < NB / 64) panel_block_update<NB, KIND>(A, R, T, b);
   }
