@@ -79,9 +79,9 @@ int32_t* trace_buffer() {
 }
 std::map<PlanKey, std::unique_ptr<DevicePlan>> g_plans;
 
-// Columns per update task: one 16-column strip per wave of the persistent
-// workgroup (8 waves), at most the tile.
-int chunk_cols(int nb) { return nb < 128 ? nb : 128; }
+// Dependency counters per tile: one per 64-column sub-chunk (an update task
+// covers two of them, a panel task publishes them one block at a time).
+int chunk_cols(int nb) { (void)nb; return 64; }
 int chunks_for(int nb) { return nb / chunk_cols(nb); }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

@@ -309,7 +309,8 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
   const int32_t ncols = nt + nrt;
   std::vector<int32_t> active(ncols, chunks);
   if (ccfg.last_a > 0 && ccfg.last_a < chunks) active[nt - 1] = ccfg.last_a;
-  const int32_t cw = prm.nb / chunks;  // columns per chunk
+  const int32_t cw = prm.nb / chunks;      // columns per counter sub-chunk
+  const int S = (prm.nb >= 128) ? 2 : 1;  // sub-chunks per update task (128 columns)
   if (nrt > 0) active[ncols - 1] = ((ccfg.nrhs_cols - (nrt - 1) * prm.nb) + cw - 1) / cw;
   const std::vector<Task> tasks = expand_tasks(mt, nt, plan.list, ncols);
   hqr_dag_info& info = plan.info;
@@ -372,30 +373,40 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
       // update: read tile (row,k) [UNMQR] or (victim,k) [TS/TT]; write (killer,j) and (row,j)
       const size_t xv = tile(t.row, t.k), xi = tile(t.row, t.j);
       const size_t xp = (t.op == UNMQR) ? 0 : tile(t.killer, t.j);
-      for (int c = 0; c < active[t.j]; ++c) {
+      // one device task per S sub-chunks of column j (only those that hold
+      // matrix columns); it waits for the factored tile's last active
+      // sub-chunk, which its panel task publishes when done
+      const int cv = active[t.k] - 1;
+      const int nu = (active[t.j] + S - 1) / S;
+      for (int u = 0; u < nu; ++u) {
+        const int c0 = u * S, cn = std::min(S, active[t.j] - c0);
         DevTask d{};
         d.op = t.op;
-        d.chunk = (uint8_t)c;
+        d.chunk = (uint8_t)u;
+        d.pad = (uint16_t)(cv | (cn << 8));
         d.row = (uint16_t)t.row;
         d.killer = (uint16_t)(t.op == UNMQR ? t.row : t.killer);
         d.k = (uint16_t)t.k;
         d.j = (uint16_t)t.j;
         d.v[0] = writes[xv];
-        add_pred(last_writer[xv * chunks]);
+        add_pred(last_writer[xv * chunks + cv]);
         if (t.op == UNMQR) {
           d.v[1] = writes[xi];
-          add_pred(last_writer[xi * chunks + c]);
         } else {
           d.v[1] = writes[xp];
           d.v[2] = writes[xi];
-          add_pred(last_writer[xp * chunks + c]);
+        }
+        for (int c = c0; c < c0 + cn; ++c) {
+          if (t.op != UNMQR) add_pred(last_writer[xp * chunks + c]);
           add_pred(last_writer[xi * chunks + c]);
         }
         const int64_t id = (int64_t)dev.size();
-        if (t.op != UNMQR) last_writer[xp * chunks + c] = id;
-        last_writer[xi * chunks + c] = id;
+        for (int c = c0; c < c0 + cn; ++c) {
+          if (t.op != UNMQR) last_writer[xp * chunks + c] = id;
+          last_writer[xi * chunks + c] = id;
+        }
         dev.push_back(d);
-        wt.push_back(op_weight(t.op));
+        wt.push_back((int64_t)op_weight(t.op) * cn);
         pred_off.push_back((int64_t)preds.size());
       }
       if (t.op != UNMQR) writes[xp]++;

@@ -46,20 +46,41 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Global-memory accessors.  The tile pointers reach the tile kernels through
-// the task records, where the compiler no longer knows their address space
-// and would emit flat instructions; flat loads also count against the LDS
-// counter, so every wait for an LDS read would wait for them as well.
+// Global-memory accessors for tile data inside the persistent launch.
+//
+// Tiles written by one workgroup are read by workgroups on other XCDs,
+// whose L2 caches are not coherent with each other.  Agent-scope
+// acquire/release fences would write back and invalidate a whole L2 at every
+// task boundary; instead every tile access is a relaxed agent-scope access
+// (coherent at device level on its own), and a task publishes its writes by
+// waiting for its stores to complete before it bumps a dependency counter.
+// The pointers are cast to the global address space: they reach the tile
+// kernels through the task records, where the compiler would otherwise emit
+// flat instructions (which also count against the LDS counter).
 #ifndef HQR_GLOBAL_AS
 #define HQR_GLOBAL_AS __attribute__((address_space(1)))
 #endif
 typedef HQR_GLOBAL_AS double gdouble;
-typedef HQR_GLOBAL_AS d2 gd2;
 
-__device__ __forceinline__ double gload(const double* p) { return *(const gdouble*)p; }
-__device__ __forceinline__ void gstore(double* p, double v) { *(gdouble*)p = v; }
-__device__ __forceinline__ d2 gload2(const double* p) { return *(const gd2*)p; }
-__device__ __forceinline__ void gstore2(double* p, d2 v) { *(gd2*)p = v; }
+__device__ __forceinline__ double gload(const double* p) {
+  return __hip_atomic_load((gdouble*)const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gstore(double* p, double v) {
+  __hip_atomic_store((gdouble*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ d2 gload2(const double* p) {
+  d2 r;
+  r.x = gload(p);
+  r.y = gload(p + 1);
+  return r;
+}
+__device__ __forceinline__ void gstore2(double* p, d2 v) {
+  gstore(p, v.x);
+  gstore(p + 1, v.y);
+}
+
+// Waits until this thread's global stores have completed.
+__device__ __forceinline__ void stores_done() { __builtin_amdgcn_s_waitcnt(0); }
 
 __device__ __forceinline__ d4 ld4(const double* p) {
   const d2 x = gload2(p);
@@ -439,6 +460,26 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
   double rv = 0.0;  // TS/TT: R(c0 + q, c0 + cc) of the killer's diagonal block
   if (KIND != K_UNM && ct && q <= cc) rv = gload(R + (c0 + q) + (int64_t)(c0 + cc) * NB);
   if (ct) Zs[cc * LDV + q] = 0.0;  // entries (i, j) with i >= j stay zero
+  // T is formed column by column on lanes 0-15 of wave 4 (idle in the column
+  // loop), one row of T per lane: column k = jj - 1 once z(0:k, k) and
+  // tau_k are visible (after the barrier of iteration jj).
+  //   T(k,k) = tau_k,  T(i,k) = -tau_k sum_{i <= l < k} T(i,l) z(l,k)
+  const bool tl = tid >= 256 && tid < 272;
+  const int ti = tid - 256;
+  double trow[16];
+#pragma unroll
+  for (int l = 0; l < 16; ++l) trow[l] = 0.0;
+  auto t_column = [&](int k) {
+    const double tk = sm.tau[k];
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < 16; ++l)
+      if (l < k) acc += trow[l] * Zs[l * LDV + k];  // trow[l] = 0 for l < ti
+    const double val = (ti < k) ? -tk * acc : (ti == k ? tk : 0.0);
+#pragma unroll
+    for (int l = 0; l < 16; ++l)
+      if (l == k) trow[l] = val;
+  };
   for (int jj = 0; jj < 16; ++jj) {
     double* vb = Vb + (jj & 1) * NB;
     if (cc == jj) {
@@ -478,6 +519,7 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
       if (q == 0) sm.tau[jj] = tau;
     }
     lds_barrier();
+    if (tl && jj > 0) t_column(jj - 1);
     if (ct && cc != jj) {
       const double tau = sm.tau[jj];
       double v[NM];
@@ -507,25 +549,13 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
     }
   }
   lds_barrier();
-  // ---- T: T(jj,jj) = tau_jj, T(0:jj, jj) = -tau_jj T(0:jj,0:jj) (V^T v_jj)(0:jj)
-  //      (Schreiber-Van Loan forward recurrence, one row of T per lane; the
-  //      sums for the later columns are accumulated as each entry appears)
-  if (tid < 16) {
-    const int i = tid;
-    double acc[16], t[16];
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const double tk = sm.tau[k];
-      t[k] = (i < k) ? -tk * acc[k] : (i == k ? tk : 0.0);
-#pragma unroll
-      for (int jj = k + 1; jj < 16; ++jj) acc[jj] += t[k] * Zs[k * LDV + jj];
-    }
+  // ---- the last column of T, then T to LDS (for the strips) and to memory
+  if (tl) {
+    t_column(15);
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
-      Ts[i * LDV + jj] = t[jj];
-      gstore(T + p * 256 + i + 16 * jj, t[jj]);
+      Ts[ti * LDV + jj] = trow[jj];
+      gstore(T + p * 256 + ti + 16 * jj, trow[jj]);
     }
   }
   // ---- the factored panel back to the tiles, and V_p into LDS
@@ -567,61 +597,48 @@ __device__ __forceinline__ void panel_strips(double* A, double* R, int p, int s_
                           NB, L);
     store_strip<NB, KIND>(acc, strip, NB, p, L);
   }
-  __syncthreads();
+  stores_done();
+  __syncthreads();  // the next panel's column loop reads these strips from memory
 }
 
-// Applies the four panels of block b (panels 4b .. 4b+3, V from the tile,
-// T from `T`) to the columns right of the block, one 16-column strip per
-// wave held in registers across the four panels.
+// Left-looking update of block b (strips 4b .. 4b+3, one per wave 0-3):
+// the panels 0 .. 4b-1 of this task are applied to it, V from the tile(s)
+// already factored and T from `T`, the strips held in registers across the
+// panels.  Done right before block b is factored, so that block b depends on
+// nothing that a predecessor task writes later than its own block b.
 template <int NB, int KIND>
-__device__ __forceinline__ void panel_block_update(double* A, double* R, const double* T, int b) {
+__device__ __forceinline__ void panel_left_update(double* A, double* R, const double* T, int b) {
   constexpr int NRB = NB / 16;
   b = __builtin_amdgcn_readfirstlane(b);
   Smem<NB>& sm = smem<NB>();
   const Lane L;
-  const int p0 = 4 * b;
-  // row blocks any of the four panels touches
-  const int lo = (KIND == K_UNM) ? p0 : 0;
-  const int hi = (KIND == K_TT) ? p0 + 3 : NRB - 1;
-  // passes over the strips right of the block, one strip per wave
-  for (int s0 = 4 * (b + 1); s0 < NRB; s0 += NT / 64) {
-    const int s = s0 + L.wave;
-    const bool on = s < NRB;  // uniform per wave
-    double* strip = A + (int64_t)(16 * s) * NB;
-    d4 acc[NRB];
+  const int np = 4 * b;  // panels applied
+  const bool on = L.wave < 4;
+  const int s = 4 * b + L.wave;
+  // row blocks the panels touch: UNM and TS all, TT rows < 16 np (below them,
+  // a TT victim holds its own GEQRT reflectors)
+  const int hi = (KIND == K_TT) ? np - 1 : NRB - 1;
+  double* strip = A + (int64_t)(16 * s) * NB;
+  d4 acc[NRB];
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb)
-      if (on && rb >= lo && rb <= hi) acc[rb] = ld4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB);
-    PanelPrefetch<NB> pf;
-    prefetch_panel<NB, KIND>(pf, A, NB, T + p0 * 256, p0);
-    for (int p = p0; p < p0 + 4; ++p) {
-      double* Vs = sm.V[p & 1];
-      double* Ts = sm.T[p & 1];
-      stage_panel<NB, KIND>(pf, Vs, Ts, p);
-      lds_barrier();
-      if (p + 1 < p0 + 4) prefetch_panel<NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
-      if (on)
-        apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
-    }
+  for (int rb = 0; rb < NRB; ++rb)
+    if (on && rb <= hi) acc[rb] = ld4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB);
+  PanelPrefetch<NB> pf;
+  prefetch_panel<NB, KIND>(pf, A, NB, T, 0);
+  for (int p = 0; p < np; ++p) {
+    double* Vs = sm.V[p & 1];
+    double* Ts = sm.T[p & 1];
+    stage_panel<NB, KIND>(pf, Vs, Ts, p);
+    lds_barrier();
+    if (p + 1 < np) prefetch_panel<NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
+    if (on)
+      apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
+  }
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb)
-      if (on && rb >= lo && rb <= hi) st4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB, acc[rb]);
-    __syncthreads();
-  }
-}
-
-template <int NB, int KIND>
-__device__ __forceinline__ void run_panel(double* A, double* R, double* T) {
-  for (int b = 0; b < NB / 64; ++b) {
-    for (int p = 4 * b; p < 4 * b + 4; ++p) {
-      panel_columns<NB, KIND>(A, R, T, p);
-      if (p < 4 * b + 3)
-        panel_strips<NB, KIND>(A, R, p, 4 * b + 3);
-      else
-        __syncthreads();  // the block update stages V from the stored columns
-    }
-    if (b + 1 < NB / 64) panel_block_update<NB, KIND>(A, R, T, b);
-  }
+  for (int rb = 0; rb < NRB; ++rb)
+    if (on && rb <= hi) st4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB, acc[rb]);
+  stores_done();
+  __syncthreads();  // the column loop of block b reads these strips from memory
 }
 
 // ---------------------------------------------------------------------------
@@ -633,7 +650,7 @@ __device__ __forceinline__ void run_panel(double* A, double* R, double* T) {
 __device__ __forceinline__ bool wait_counter(int32_t* c, uint32_t v, const LaunchArgs& a, int64_t& spins, int t) {
   if (v == 0) return true;
   for (;;) {
-    const uint32_t seen = (uint32_t)__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t seen = (uint32_t)__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (seen >= v) return true;
     ++spins;
     if (spins > a.spin_limit) {
@@ -707,35 +724,52 @@ __device__ __noinline__ int take_task(const LaunchArgs& a) {
   return __builtin_amdgcn_readfirstlane(sm.task);
 }
 
-// Thread 0 waits for the task's input versions; returns 1 (uniform) when
-// they were reached, 0 when the launch was aborted.
+// Dependency counters count 64-column sub-chunks of a tile.  A panel task
+// works through its tile(s) block by block (64 columns each): it waits for
+// block b's sub-chunk before touching block b and publishes it when the
+// block is final, so a chain of panel tasks on one tile (a TS domain, a
+// tree) advances one block behind its predecessor.  The last active
+// sub-chunk is published only when the whole task is done, which is what
+// the update tasks reading the factored tile wait for (task.pad & 0xff).
+// An update task covers task.pad >> 8 sub-chunks starting at chunk * S.
+
+// Thread 0 waits for the task's input versions (panel tasks: block 0);
+// returns 1 (uniform) when they were reached, 0 when the launch was aborted.
 template <int NB>
 __device__ __noinline__ int wait_task(const LaunchArgs& a, int t, const DevTask& task) {
   Smem<NB>& sm = smem<NB>();
   if (threadIdx.x == 0) {
-    const int op = task.op, ch = task.chunk, i = task.row, piv = task.killer, k = task.k, j = task.j;
-    const int C = task.chunk;  // panel tasks: active chunks of the tile column
+    const int op = task.op, i = task.row, piv = task.killer, k = task.k, j = task.j;
     int64_t spins = 0;
     bool ok = true;
-    switch (op) {
-      case GEQRT:
-        for (int c = 0; c < C && ok; ++c) ok = wait_counter(counter(a, i, k, c), task.v[0], a, spins, t);
-        break;
-      case UNMQR:
-        ok = wait_counter(counter(a, i, k, 0), task.v[0], a, spins, t) &&
-             wait_counter(counter(a, i, j, ch), task.v[1], a, spins, t);
-        break;
-      case TSQRT:
-      case TTQRT:
-        for (int c = 0; c < C && ok; ++c)
-          ok = wait_counter(counter(a, piv, k, c), task.v[0], a, spins, t) &&
-               wait_counter(counter(a, i, k, c), task.v[1], a, spins, t);
-        break;
-      default:
-        ok = wait_counter(counter(a, i, k, 0), task.v[0], a, spins, t) &&
-             wait_counter(counter(a, piv, j, ch), task.v[1], a, spins, t) &&
-             wait_counter(counter(a, i, j, ch), task.v[2], a, spins, t);
-        break;
+    if (a.B) {
+      // apply launch: one counter per block of B
+      ok = (op == UNMQR) ? wait_counter(counter(a, i, j, 0), task.v[1], a, spins, t)
+                         : wait_counter(counter(a, piv, j, 0), task.v[1], a, spins, t) &&
+                               wait_counter(counter(a, i, j, 0), task.v[2], a, spins, t);
+    } else {
+      const int S = (NB >= 128) ? 2 : 1;  // sub-chunks per update task
+      const int c0 = task.chunk * S, cn = task.pad >> 8, cv = task.pad & 0xff;
+      switch (op) {
+        case GEQRT:
+          ok = wait_counter(counter(a, i, k, 0), task.v[0], a, spins, t);
+          break;
+        case TSQRT:
+        case TTQRT:
+          ok = wait_counter(counter(a, piv, k, 0), task.v[0], a, spins, t) &&
+               wait_counter(counter(a, i, k, 0), task.v[1], a, spins, t);
+          break;
+        case UNMQR:
+          ok = wait_counter(counter(a, i, k, cv), task.v[0], a, spins, t);
+          for (int c = c0; c < c0 + cn && ok; ++c) ok = wait_counter(counter(a, i, j, c), task.v[1], a, spins, t);
+          break;
+        default:
+          ok = wait_counter(counter(a, i, k, cv), task.v[0], a, spins, t);
+          for (int c = c0; c < c0 + cn && ok; ++c)
+            ok = wait_counter(counter(a, piv, j, c), task.v[1], a, spins, t) &&
+                 wait_counter(counter(a, i, j, c), task.v[2], a, spins, t);
+          break;
+      }
     }
     sm.ok = ok ? 1 : 0;
     trace(a, t, ok ? TR_READY : TR_ABORT);
@@ -743,41 +777,82 @@ __device__ __noinline__ int wait_task(const LaunchArgs& a, int t, const DevTask&
   }
   __syncthreads();
   const int ok = __builtin_amdgcn_readfirstlane(sm.ok);
-  // the tiles written by the producers are visible from here on
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  // the producers' stores had completed when they bumped the counters, and
+  // tile loads are device-coherent: no cache invalidation is needed
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   return ok;
 }
 
+// Panel tasks, inside the task: wait for block b (b >= 1) of the tile(s).
+template <int NB>
+__device__ __noinline__ int wait_block(const LaunchArgs& a, int t, const DevTask& task, int b) {
+  Smem<NB>& sm = smem<NB>();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t spins = 0;
+    bool ok = true;
+    if (task.op == GEQRT)
+      ok = wait_counter(counter(a, task.row, task.k, b), task.v[0], a, spins, t);
+    else
+      ok = wait_counter(counter(a, task.killer, task.k, b), task.v[0], a, spins, t) &&
+           wait_counter(counter(a, task.row, task.k, b), task.v[1], a, spins, t);
+    sm.ok = ok ? 1 : 0;
+  }
+  __syncthreads();
+  const int ok = __builtin_amdgcn_readfirstlane(sm.ok);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  return ok;
+}
+
+// Panel tasks, inside the task: block b of the tile(s) is final.
+template <int NB>
+__device__ __noinline__ void release_block(const LaunchArgs& a, const DevTask& task, int b) {
+  stores_done();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(counter(a, task.row, task.k, b), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (task.op != GEQRT)
+      __hip_atomic_fetch_add(counter(a, task.killer, task.k, b), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // Publishes the task's tile writes and bumps the counters of the tiles it
-// wrote.
+// wrote (panel tasks: the last active block; the others went out with
+// release_block).
 template <int NB>
 __device__ __noinline__ void finish_task(const LaunchArgs& a, int t, const DevTask& task) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  stores_done();
   __syncthreads();
   if (threadIdx.x == 0) {
     trace(a, t, TR_DONE);
     stamp(a, t, 2);
-    const int op = task.op, ch = task.chunk, i = task.row, piv = task.killer, k = task.k, j = task.j;
-    const int C = task.chunk;  // panel tasks: active chunks of the tile column
-    auto bump = [&](int32_t* c) { __hip_atomic_fetch_add(c, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); };
-    switch (op) {
-      case GEQRT:
-        for (int c = 0; c < C; ++c) bump(counter(a, i, k, c));
-        break;
-      case UNMQR:
-        bump(counter(a, i, j, ch));
-        break;
-      case TSQRT:
-      case TTQRT:
-        for (int c = 0; c < C; ++c) {
-          bump(counter(a, piv, k, c));
-          bump(counter(a, i, k, c));
-        }
-        break;
-      default:
-        bump(counter(a, piv, j, ch));
-        bump(counter(a, i, j, ch));
-        break;
+    const int op = task.op, i = task.row, piv = task.killer, k = task.k, j = task.j;
+    auto bump = [&](int32_t* c) { __hip_atomic_fetch_add(c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    if (a.B) {
+      if (op != UNMQR) bump(counter(a, piv, j, 0));
+      bump(counter(a, i, j, 0));
+    } else {
+      const int S = (NB >= 128) ? 2 : 1;
+      const int c0 = task.chunk * S, cn = task.pad >> 8;
+      switch (op) {
+        case GEQRT:
+          bump(counter(a, i, k, task.chunk - 1));
+          break;
+        case TSQRT:
+        case TTQRT:
+          bump(counter(a, piv, k, task.chunk - 1));
+          bump(counter(a, i, k, task.chunk - 1));
+          break;
+        case UNMQR:
+          for (int c = c0; c < c0 + cn; ++c) bump(counter(a, i, j, c));
+          break;
+        default:
+          for (int c = c0; c < c0 + cn; ++c) {
+            bump(counter(a, piv, j, c));
+            bump(counter(a, i, j, c));
+          }
+          break;
+      }
     }
   }
 }
@@ -794,15 +869,37 @@ __device__ __forceinline__ double* t_block(double* T, const LaunchArgs& a, int n
 
 // One tile kernel per function (each gets its own register allocation).
 // Panel tasks are on the critical path of the factorization: their waves
-// run at raised priority so a co-resident update task yields issue slots.
+// run at raised priority.  The tile(s) are processed block by block (64
+// columns), left-looking: block b waits for the predecessor's block b,
+// takes this task's earlier panels, is factored, and is published at once
+// (except the last active block, published by finish_task).  Returns 0 when
+// the launch was aborted while waiting.
 template <int NB, int KIND>
-__device__ __noinline__ void panel_task(const LaunchArgs& a, const DevTask& task) {
-  double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
+__device__ __noinline__ int panel_task(const LaunchArgs& a, int t, const DevTask& task) {
+  double* T = t_block((KIND == K_UNM) ? a.Tg : a.Tk, a, NB, task.row, task.k);
+  double* A = tile_ptr(a, NB, task.row, task.k);
+  double* R = KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.k);
+  const int active = task.chunk;  // blocks holding matrix columns
   __builtin_amdgcn_s_setprio(2);
-  run_panel<NB, KIND>(tile_ptr(a, NB, task.row, task.k),
-                      KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.k),
-                      t_block(T, a, NB, task.row, task.k));
+  for (int b = 0; b < NB / 64; ++b) {
+    if (b > 0 && b < active && !wait_block<NB>(a, t, task, b)) {
+      __builtin_amdgcn_s_setprio(0);
+      return 0;
+    }
+    if (b > 0) panel_left_update<NB, KIND>(A, R, T, b);
+    for (int p = 4 * b; p < 4 * b + 4; ++p) {
+      panel_columns<NB, KIND>(A, R, T, p);
+      if (p < 4 * b + 3) panel_strips<NB, KIND>(A, R, p, 4 * b + 3);
+    }
+    if (b + 1 < active) {
+      release_block<NB>(a, task, b);
+    } else {
+      stores_done();
+      __syncthreads();  // the next block reads the columns and T stored by this one
+    }
+  }
   __builtin_amdgcn_s_setprio(0);
+  return 1;
 }
 
 // An update task covers one column chunk: 128 columns (one 16-column strip
@@ -844,6 +941,7 @@ __global__ __launch_bounds__(NT, 1) void persistent_kernel(LaunchArgs a) {
     if (t < 0) break;
     const DevTask task = a.tasks[t];
     if (!wait_task<NB>(a, t, task)) break;
+    int ok = 1;
     if (a.B) {
       if (a.trans) {
         switch (task.op) {
@@ -860,14 +958,15 @@ __global__ __launch_bounds__(NT, 1) void persistent_kernel(LaunchArgs a) {
       }
     } else {
       switch (task.op) {
-        case GEQRT: panel_task<NB, K_UNM>(a, task); break;
-        case TSQRT: panel_task<NB, K_TS>(a, task); break;
-        case TTQRT: panel_task<NB, K_TT>(a, task); break;
+        case GEQRT: ok = panel_task<NB, K_UNM>(a, t, task); break;
+        case TSQRT: ok = panel_task<NB, K_TS>(a, t, task); break;
+        case TTQRT: ok = panel_task<NB, K_TT>(a, t, task); break;
         case UNMQR: update_task<NB, K_UNM>(a, task); break;
         case TSMQR: update_task<NB, K_TS>(a, task); break;
         default: update_task<NB, K_TT>(a, task); break;
       }
     }
+    if (!ok) break;  // aborted inside a panel task
     finish_task<NB>(a, t, task);
   }
 }
