@@ -82,19 +82,38 @@ __device__ __forceinline__ void gstore2(double* p, d2 v) {
 // Waits until this thread's global stores have completed.
 __device__ __forceinline__ void stores_done() { __builtin_amdgcn_s_waitcnt(0); }
 
-__device__ __forceinline__ d4 ld4(const double* p) {
-  const d2 x = gload2(p);
-  const d2 y = gload2(p + 2);
-  d4 r;
-  r.x = x.x; r.y = x.y; r.z = y.x; r.w = y.y;
-  return r;
-}
+// 16-byte device-coherent accesses through a buffer resource: `base` is
+// wave-uniform, `off` the element offset of this lane (< 2^28).
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+constexpr int kCoherent = 16;  // cache policy bit: coherent at device scope
 
-__device__ __forceinline__ void st4(double* p, d4 v) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const double* base) {
+  // the base is wave-uniform by construction; say so, so that it lives in
+  // scalar registers
+  const uint64_t u = (uint64_t)base;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  double* b = (double*)(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(b, 0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ d2 bload2(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off * 8, 0, kCoherent));
+}
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, int off, d2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off * 8, 0, kCoherent);
+}
+__device__ __forceinline__ d4 ld4(__amdgpu_buffer_rsrc_t r, int off) {
+  const d2 x = bload2(r, off);
+  const d2 y = bload2(r, off + 2);
+  d4 v;
+  v.x = x.x; v.y = x.y; v.z = y.x; v.w = y.y;
+  return v;
+}
+__device__ __forceinline__ void st4(__amdgpu_buffer_rsrc_t r, int off, d4 v) {
   d2 x, y;
   x.x = v.x; x.y = v.y; y.x = v.z; y.y = v.w;
-  gstore2(p, x);
-  gstore2(p + 2, y);
+  bstore2(r, off, x);
+  bstore2(r, off + 2, y);
 }
 
 // One DPP step on a double: each lane receives the value of the lane picked
@@ -151,7 +170,7 @@ struct Lane {
   int wave, g, q, pq;
   __device__ Lane() {
     const int t = threadIdx.x;
-    wave = t >> 6;
+    wave = __builtin_amdgcn_readfirstlane(t >> 6);
     g = (t >> 4) & 3;
     q = t & 15;
     pq = 4 * (q & 3) + (q >> 2);
@@ -190,10 +209,11 @@ __device__ __forceinline__ void apply_panel_n(d4 (&acc)[SPW][NB / 16], const dou
   constexpr int NRB = NB / 16;
   d4 c1v[SPW];
   d4 w0[SPW], w1[SPW];
+  const __amdgpu_buffer_rsrc_t rc1 = rsrc(c1);
 #pragma unroll
   for (int s = 0; s < SPW; ++s) {
     c1v[s] = d4{0.0, 0.0, 0.0, 0.0};
-    if (KIND != K_UNM) c1v[s] = ld4(c1 + 4 * L.g + (int64_t)(L.q + 64 * s) * ldc);
+    if (KIND != K_UNM) c1v[s] = ld4(rc1, 4 * L.g + (L.q + 64 * s) * (int)ldc);
     w0[s] = d4{0.0, 0.0, 0.0, 0.0};
     w1[s] = w0[s];
   }
@@ -246,7 +266,7 @@ __device__ __forceinline__ void apply_panel_n(d4 (&acc)[SPW][NB / 16], const dou
       d4 w2t = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int r = 0; r < 4; ++r) w2t = mfma(t[r], w[r], w2t);
-      if (KIND != K_UNM) st4(c1 + 4 * L.g + (int64_t)(L.q + 64 * s) * ldc, c1v[s] - w2t);
+      if (KIND != K_UNM) st4(rc1, 4 * L.g + (L.q + 64 * s) * (int)ldc, c1v[s] - w2t);
       wn[s] = -w2t;
     }
   }
@@ -293,7 +313,7 @@ __device__ __forceinline__ void load_strip(d4 (&acc)[NB / 16], const double* bas
 #pragma unroll
   for (int rb = 0; rb < NB / 16; ++rb) {
     const bool active = (KIND == K_UNM) ? (rb >= p) : (KIND == K_TT ? rb <= p : true);
-    if (active) acc[rb] = ld4(base + 16 * rb + 4 * L.g + (int64_t)L.q * ld);
+    if (active) acc[rb] = ld4(rsrc(base), 16 * rb + 4 * L.g + L.q * (int)ld);
   }
 }
 
@@ -303,7 +323,7 @@ __device__ __forceinline__ void store_strip(const d4 (&acc)[NB / 16], double* ba
 #pragma unroll
   for (int rb = 0; rb < NB / 16; ++rb) {
     const bool active = (KIND == K_UNM) ? (rb >= p) : (KIND == K_TT ? rb <= p : true);
-    if (active) st4(base + 16 * rb + 4 * L.g + (int64_t)L.q * ld, acc[rb]);
+    if (active) st4(rsrc(base), 16 * rb + 4 * L.g + L.q * (int)ld, acc[rb]);
   }
 }
 
@@ -327,7 +347,7 @@ __device__ __forceinline__ void prefetch_panel(PanelPrefetch<NB>& pf, const doub
     const int e = it * NT + tid;
     const int col = e / (NB / 2), row = 2 * (e % (NB / 2));
     const bool needed = (KIND == K_UNM) ? (row >= 16 * p) : (KIND == K_TT ? row < 16 * p + 16 : true);
-    if (needed) pf.v[it] = gload2(V + row + (int64_t)(16 * p + col) * ld);
+    if (needed) pf.v[it] = bload2(rsrc(V), row + (16 * p + col) * (int)ld);
   }
   if (tid < 256) pf.t = gload(Tblk + tid);
 }
@@ -622,7 +642,7 @@ __device__ __forceinline__ void panel_left_update(double* A, double* R, const do
   d4 acc[NRB];
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb)
-    if (on && rb <= hi) acc[rb] = ld4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB);
+    if (on && rb <= hi) acc[rb] = ld4(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB);
   PanelPrefetch<NB> pf;
   prefetch_panel<NB, KIND>(pf, A, NB, T, 0);
   for (int p = 0; p < np; ++p) {
@@ -636,7 +656,7 @@ __device__ __forceinline__ void panel_left_update(double* A, double* R, const do
   }
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb)
-    if (on && rb <= hi) st4(strip + 16 * rb + 4 * L.g + (int64_t)L.q * NB, acc[rb]);
+    if (on && rb <= hi) st4(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB, acc[rb]);
   stores_done();
   __syncthreads();  // the column loop of block b reads these strips from memory
 }
