@@ -29,7 +29,7 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
 # copy-in kernel of known size.  Valid only for the kernel source they were
 # measured on (first 16 hex digits of the SHA-256 of csrc/kernels.hip).
 TRAFFIC = {
-    "tall-hqr": {"kernels_sha256": "c26ad87963c67b8e", "read": 41.85e9, "write": 30.81e9,
+    "tall-hqr": {"kernels_sha256": "9ccd2e7c360edbfe", "read": 46.17e9, "write": 49.56e9,
                  "profile": "profiles/persistent_kernel_tall-hqr.md"},
 }
 
