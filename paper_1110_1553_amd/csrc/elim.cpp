@@ -382,7 +382,7 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
         const int c0 = u * S, cn = std::min(S, active[t.j] - c0);
         DevTask d{};
         d.op = t.op;
-        d.chunk = (uint8_t)u;
+        d.chunk = (uint8_t)c0;
         d.pad = (uint16_t)(cv | (cn << 8));
         d.row = (uint16_t)t.row;
         d.killer = (uint16_t)(t.op == UNMQR ? t.row : t.killer);

@@ -93,9 +93,10 @@ struct ColumnChunks {
 // program order.  `chunks` = dependency counters per tile (64-column
 // sub-chunks).  A panel task's `chunk` field holds the number of active
 // sub-chunks of its tile column (the blocks it waits for and publishes one
-// by one).  An update task covers 128 columns (two sub-chunks; 64 at
-// nb = 64): `chunk` is its index, `pad` = (sub-chunks covered << 8) | the
-// factored tile's last active sub-chunk, which it waits for.
+// by one).  An update task covers 128 columns (two sub-chunks; one at
+// nb = 64 or at the ragged end of a tile): `chunk` is its first sub-chunk,
+// `pad` = (sub-chunks covered << 8) | the factored tile's last active
+// sub-chunk, which it waits for.
 int build_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, int chunks, Plan& plan,
                const ColumnChunks& cc = ColumnChunks());
 

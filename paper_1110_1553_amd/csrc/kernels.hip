@@ -751,7 +751,8 @@ __device__ __noinline__ int take_task(const LaunchArgs& a) {
 // tree) advances one block behind its predecessor.  The last active
 // sub-chunk is published only when the whole task is done, which is what
 // the update tasks reading the factored tile wait for (task.pad & 0xff).
-// An update task covers task.pad >> 8 sub-chunks starting at chunk * S.
+// An update task covers task.pad >> 8 sub-chunks starting at sub-chunk
+// task.chunk.
 
 // Thread 0 waits for the task's input versions (panel tasks: block 0);
 // returns 1 (uniform) when they were reached, 0 when the launch was aborted.
@@ -768,8 +769,7 @@ __device__ __noinline__ int wait_task(const LaunchArgs& a, int t, const DevTask&
                          : wait_counter(counter(a, piv, j, 0), task.v[1], a, spins, t) &&
                                wait_counter(counter(a, i, j, 0), task.v[2], a, spins, t);
     } else {
-      const int S = (NB >= 128) ? 2 : 1;  // sub-chunks per update task
-      const int c0 = task.chunk * S, cn = task.pad >> 8, cv = task.pad & 0xff;
+      const int c0 = task.chunk, cn = task.pad >> 8, cv = task.pad & 0xff;
       switch (op) {
         case GEQRT:
           ok = wait_counter(counter(a, i, k, 0), task.v[0], a, spins, t);
@@ -852,8 +852,7 @@ __device__ __noinline__ void finish_task(const LaunchArgs& a, int t, const DevTa
       if (op != UNMQR) bump(counter(a, piv, j, 0));
       bump(counter(a, i, j, 0));
     } else {
-      const int S = (NB >= 128) ? 2 : 1;
-      const int c0 = task.chunk * S, cn = task.pad >> 8;
+      const int c0 = task.chunk, cn = task.pad >> 8;
       switch (op) {
         case GEQRT:
           bump(counter(a, i, k, task.chunk - 1));
@@ -922,16 +921,20 @@ __device__ __noinline__ int panel_task(const LaunchArgs& a, int t, const DevTask
   return 1;
 }
 
-// An update task covers one column chunk: 128 columns (one 16-column strip
-// per wave) for tiles of 128 or 256, the whole tile for nb = 64.
+// An update task covers one or two 64-column sub-chunks (one 16-column
+// strip per wave; one sub-chunk at nb = 64 and at the ragged end of a tile).
 template <int NB, int KIND>
 __device__ __noinline__ void update_task(const LaunchArgs& a, const DevTask& task) {
-  constexpr int CW = NB < 128 ? NB : 128;
   double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
-  const int64_t colchunk = (int64_t)task.chunk * CW * NB;
-  run_update<NB, KIND, true, CW>(smem<NB>(), tile_ptr(a, NB, task.row, task.k), t_block(T, a, NB, task.row, task.k),
-                                 KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.j) + colchunk,
-                                 tile_ptr(a, NB, task.row, task.j) + colchunk, NB);
+  const int64_t colchunk = (int64_t)task.chunk * 64 * NB;
+  const double* V = tile_ptr(a, NB, task.row, task.k);
+  const double* Tb = t_block(T, a, NB, task.row, task.k);
+  double* C1 = KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.j) + colchunk;
+  double* C2 = tile_ptr(a, NB, task.row, task.j) + colchunk;
+  if (NB >= 128 && (task.pad >> 8) == 2)
+    run_update<NB, KIND, true, 128>(smem<NB>(), V, Tb, C1, C2, NB);
+  else
+    run_update<NB, KIND, true, 64>(smem<NB>(), V, Tb, C1, C2, NB);
 }
 
 // Block of 64 columns of B (nb x 64, column-major) of tile row r.
