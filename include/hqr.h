@@ -249,6 +249,89 @@ int hqr_lstsq_workspace_size(int64_t M, int64_t N, int32_t nrhs, const hqr_param
 int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t ldb, int32_t nrhs,
               const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
 
+/* ---- Batched problems (one persistent launch for many small QRs) ----
+ *
+ * Many independent factorizations or least-squares solves, each with its own
+ * shape (M_q x N_q, M_q >= N_q) and right-hand sides, run as one batch: one
+ * copy-in launch, one persistent launch whose task list is the union of the
+ * problems' task graphs (Algorithm 2 per problem, merged by the same
+ * critical-path priority that orders one problem's tasks, each problem's own
+ * order kept), one back-substitution launch and one copy-out launch.  All
+ * problems of a batch share one hqr_params (one tile size nb).  The batch
+ * object holds the host plan; the caller owns every device buffer.  Results
+ * per problem are those of hqr_lstsq (nrhs_q > 0) or hqr_factor (nrhs_q = 0)
+ * on that problem alone. */
+typedef struct hqr_batch hqr_batch;
+
+/* Plans a batch of `count` (1..65535) problems: M[q] x N[q] matrices with
+ * nrhs[q] right-hand sides each (nrhs may be NULL: no right-hand sides,
+ * factorization only).  Host memory only; nothing is enqueued.  Errors: -1
+ * count out of range, -2 M NULL or some M[q] < 1 (or too many tile rows), -3
+ * N NULL or some N[q] < 1 or > M[q], -4 some nrhs[q] < 0, -5 bad params, -6
+ * bad exec.order, -7 out NULL. */
+int hqr_batch_create(int32_t count, const int64_t* M, const int64_t* N, const int32_t* nrhs,
+                     const hqr_params* params, const hqr_exec* exec, hqr_batch** out);
+
+/* Device workspace bytes of the batch (control words, per-problem status,
+ * dependency counters, task list, and per problem the T factors and the
+ * tiles of A and B).  Errors: -1 b NULL, -2 bytes NULL. */
+int hqr_batch_workspace_size(const hqr_batch* b, size_t* bytes);
+
+/* The merged task list of the batch in dispatch order (records as
+ * hqr_plan_tasks) and the problem index of each task; either output may be
+ * NULL, both NULL only counts.  Errors: -1 b NULL, -4 cap too small, -5
+ * count NULL. */
+int hqr_batch_num_tasks(const hqr_batch* b, hqr_task* tasks, int32_t* prob, int64_t cap, int64_t* count);
+
+/* Binds the caller's matrices to the batch: host arrays of `count` device
+ * pointers dA[q] (column-major, leading dimension lda[q] >= M[q]) and dB[q]
+ * (ldb[q] >= M[q]; dB and ldb may be NULL when no problem has right-hand
+ * sides, and dB[q] is ignored when nrhs[q] = 0), and the workspace dwork.
+ * Enqueues on `stream` the upload of the problem descriptors and the task
+ * list into dwork (from library-owned pinned host memory).  Not
+ * graph-capturable; the batch may be run any number of times after one
+ * bind.  Errors: -1 b NULL, -2 dA NULL or an entry NULL, -3 lda NULL or an
+ * entry < M[q], -4 dB missing where needed, -5 ldb missing or an entry <
+ * M[q], -6 dwork NULL, -7 work_bytes too small. */
+int hqr_batch_bind(hqr_batch* b, double* const* dA, const int64_t* lda, double* const* dB, const int64_t* ldb,
+                   void* dwork, size_t work_bytes, void* stream);
+
+/* Runs the bound batch on `stream`: copies every A_q (and B_q) into the
+ * workspace, factors all problems in one persistent launch, solves
+ * R_q x = (Q_q^T B_q)(0:N_q) for problems with right-hand sides, and copies
+ * A_q (R and V as after hqr_factor) and B_q (x in rows 0..N_q-1, the
+ * residual components below) back.  Only kernel launches are enqueued (no
+ * host work, copies or memsets), so the call can be captured into a HIP
+ * graph and replayed; each replay starts again from the caller's A_q and
+ * B_q.  Errors: -1 b NULL, -2 dwork NULL or not the workspace of the last
+ * bind, -3 work_bytes too small. */
+int hqr_batch_run(const hqr_batch* b, void* dwork, size_t work_bytes, void* stream);
+
+/* Waits for the stream (timeout_s as hqr_status_ex) and reports the batch
+ * status in *status (0, HQR_ERR_WATCHDOG, or HQR_ERR_SINGULAR when some
+ * problem's R has a zero diagonal entry) and, if first_zero is not NULL,
+ * per problem the index of its first zero diagonal entry of R, or -1.
+ * Errors: -1 b NULL, -2 dwork NULL, -5 status NULL; HQR_ERR_TIMEOUT. */
+int hqr_batch_status(const hqr_batch* b, const void* dwork, void* stream, double timeout_s, int32_t* status,
+                     int32_t* first_zero);
+
+/* Frees the host batch object (the caller's device buffers are untouched). */
+void hqr_batch_destroy(hqr_batch* b);
+
+/* One-call batched least squares: create, bind and run a batch, then free
+ * it (the work stays enqueued).  Arguments as hqr_batch_create/_bind; nrhs
+ * may be NULL (factorizations only).  Errors: -1 count out of range, -2 dA,
+ * -3 M, -4 N, -5 lda, -6 dB, -7 ldb, -8 nrhs, -9 params, -10 exec.order, -11
+ * dwork NULL, -12 work_bytes too small (hqr_lstsq_batched_workspace_size). */
+int hqr_lstsq_batched(int32_t count, double* const* dA, const int64_t* M, const int64_t* N, const int64_t* lda,
+                      double* const* dB, const int64_t* ldb, const int32_t* nrhs, const hqr_params* params,
+                      const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
+
+/* Workspace bytes of hqr_lstsq_batched.  Errors as hqr_batch_create (-1 .. -5),
+ * -6 bytes NULL. */
+int hqr_lstsq_batched_workspace_size(int32_t count, const int64_t* M, const int64_t* N, const int32_t* nrhs,
+                                     const hqr_params* params, size_t* bytes);
+
 /* Status word of the last launch that used the workspace `dwork` (a
  * factorization or least-squares workspace, or the bwork of hqr_apply_qt/_q):
  * waits for the stream (at most 300 s), then reports 0, HQR_ERR_WATCHDOG or

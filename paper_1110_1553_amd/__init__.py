@@ -7,6 +7,8 @@ this package only marshals arguments to it:
   persistent GPU launch driven by a hierarchical elimination tree;
 * :func:`apply_qt`, :func:`apply_q` -- B <- Q^T B and B <- Q B with a
   finished factorization; :func:`lstsq` -- least squares through both;
+* :func:`lstsq_batched`, :class:`BatchedLstsq` -- many independent small
+  least-squares problems (or factorizations) in one persistent launch;
 * :func:`elimlist`, :func:`validate`, :func:`dag_stats` -- the elimination
   lists and task graphs the library builds on the host.
 
@@ -20,7 +22,7 @@ from ._lib import (BINARY, CHAIN, FIBONACCI, FLAT, GREEDY, OPS, Exec, HQRError, 
 __all__ = ["FLAT", "BINARY", "GREEDY", "FIBONACCI", "CHAIN", "OPS", "Params", "Exec", "HQRError", "make_params",
            "make_exec", "elimlist", "validate", "dag_stats", "workspace_size", "apply_workspace_size",
            "lstsq_workspace_size", "factor",
-           "apply_qt", "apply_q", "lstsq", "colmajor", "r_of", "Workspace", "ApplyWorkspace", "status",
+           "apply_qt", "apply_q", "lstsq", "lstsq_batched", "BatchedLstsq", "colmajor", "r_of", "Workspace", "ApplyWorkspace", "status",
            "release_plans", "version"]
 
 
@@ -164,3 +166,62 @@ def r_of(A):
     M, N = A.shape
     Rt = A[:N, :N].detach().cpu().numpy()
     return np.triu(Rt)
+
+
+class BatchedLstsq:
+    """Independent least-squares problems min ||A_q X_q - B_q|| (or, with
+    ``Bs`` None, factorizations of the A_q) on fixed device buffers, run as
+    one batch: planned and bound to the buffers once, then :meth:`run` any
+    number of times.  ``run`` enqueues kernel launches only (it can be
+    captured in a graph); every run starts again from the current contents
+    of the A_q and B_q and overwrites them as :func:`lstsq` does."""
+
+    def __init__(self, As, Bs, params, exec_=None, stream=None):
+        import torch
+
+        shapes = [_colmajor_args(A, "A[%d]" % q) for q, A in enumerate(As)]
+        rhs = [_colmajor_args(B, "B[%d]" % q) for q, B in enumerate(Bs)] if Bs is not None else None
+        if rhs is not None:
+            if len(rhs) != len(shapes):
+                raise ValueError("As and Bs differ in length")
+            for q, (sa, sb) in enumerate(zip(shapes, rhs)):
+                if sa[0] != sb[0]:
+                    raise ValueError("B[%d] must have %d rows" % (q, sa[0]))
+        self.As, self.Bs = list(As), (list(Bs) if Bs is not None else None)
+        M = [sh[0] for sh in shapes]
+        N = [sh[1] for sh in shapes]
+        nrhs = [sb[1] for sb in rhs] if rhs is not None else None
+        self.batch = _lib.Batch(M, N, nrhs, params, exec_)
+        self.bytes = self.batch.workspace_size()
+        device = As[0].device
+        self.work = torch.empty(self.bytes, dtype=torch.uint8, device=device)
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.batch.bind([A.data_ptr() for A in As], [sh[2] for sh in shapes],
+                        [B.data_ptr() for B in Bs] if Bs is not None else None,
+                        [sb[2] for sb in rhs] if rhs is not None else None,
+                        self.work.data_ptr(), self.bytes, s.cuda_stream)
+
+    def run(self, stream=None):
+        import torch
+
+        s = stream if stream is not None else torch.cuda.current_stream(self.work.device)
+        self.batch.run(self.work.data_ptr(), self.bytes, s.cuda_stream)
+
+    def status(self, stream=None, timeout_s=0.0):
+        """(status word, per problem the first zero diagonal index of R or -1)."""
+        import torch
+
+        s = stream if stream is not None else torch.cuda.current_stream(self.work.device)
+        return self.batch.status(self.work.data_ptr(), s.cuda_stream, timeout_s)
+
+
+def lstsq_batched(As, Bs, params, exec_=None, stream=None, check=True):
+    """Solves every problem of a batch in place (see :class:`BatchedLstsq`)
+    and returns, per problem, the index of the first zero diagonal entry of
+    R or -1.  With ``check`` a watchdog abort raises HQRError."""
+    solver = BatchedLstsq(As, Bs, params, exec_, stream)
+    solver.run(stream)
+    st, first_zero = solver.status(stream)
+    if check and st not in (0, _lib.ERR_SINGULAR):
+        raise HQRError("hqr_batch_run (device)", st)
+    return first_zero

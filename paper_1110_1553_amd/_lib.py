@@ -43,7 +43,9 @@ TASK_DTYPE = np.dtype([("op", "u1"), ("chunk", "u1"), ("row", "<u2"), ("killer",
 
 EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size", "hqr_factor",
            "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size", "hqr_lstsq",
-           "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_timeline", "hqr_version")
+           "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_timeline", "hqr_version",
+           "hqr_batch_create", "hqr_batch_workspace_size", "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run",
+           "hqr_batch_status", "hqr_batch_destroy", "hqr_lstsq_batched", "hqr_lstsq_batched_workspace_size")
 
 _lib = None
 
@@ -76,6 +78,16 @@ def load():
     lib.hqr_apply_q.argtypes = apply_args
     lib.hqr_lstsq_workspace_size.argtypes = [i64, i64, i32, P(Params), P(ctypes.c_size_t)]
     lib.hqr_lstsq.argtypes = [vp, i64, i64, i64, vp, i64, i32, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
+    lib.hqr_batch_create.argtypes = [i32, vp, vp, vp, P(Params), P(Exec), P(vp)]
+    lib.hqr_batch_workspace_size.argtypes = [vp, P(ctypes.c_size_t)]
+    lib.hqr_batch_num_tasks.argtypes = [vp, vp, vp, i64, P(i64)]
+    lib.hqr_batch_bind.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.hqr_batch_run.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.hqr_batch_status.argtypes = [vp, vp, vp, ctypes.c_double, P(i32), vp]
+    lib.hqr_batch_destroy.argtypes = [vp]
+    lib.hqr_batch_destroy.restype = None
+    lib.hqr_lstsq_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
+    lib.hqr_lstsq_batched_workspace_size.argtypes = [i32, vp, vp, vp, P(Params), P(ctypes.c_size_t)]
     lib.hqr_status.argtypes = [vp, vp, P(i32)]
     lib.hqr_status_ex.argtypes = [vp, vp, ctypes.c_double, P(i32), P(i32)]
     lib.hqr_release_plans.argtypes = []
@@ -90,8 +102,9 @@ def load():
     lib.hqr_version.restype = ctypes.c_char_p
     for name in ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size",
                  "hqr_factor", "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size",
-                 "hqr_lstsq", "hqr_status",
-                 "hqr_status_ex"):
+                 "hqr_lstsq", "hqr_status", "hqr_status_ex", "hqr_batch_create", "hqr_batch_workspace_size",
+                 "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run", "hqr_batch_status", "hqr_lstsq_batched",
+                 "hqr_lstsq_batched_workspace_size"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -219,6 +232,104 @@ def timeline(stream: int) -> np.ndarray:
         _check("hqr_timeline", lib.hqr_timeline(ctypes.c_void_p(stream), ctypes.c_void_p(out.ctypes.data), n.value,
                                                 ctypes.byref(n)))
     return out
+
+
+def _i64(xs):
+    return np.ascontiguousarray(np.asarray(xs, dtype=np.int64))
+
+
+def _i32(xs):
+    return np.ascontiguousarray(np.asarray(xs, dtype=np.int32))
+
+
+def _ptr(arr):
+    return ctypes.c_void_p(arr.ctypes.data) if arr is not None else None
+
+
+class Batch:
+    """A planned batch of independent problems (hqr_batch_create); the
+    shapes are M[q] x N[q] with nrhs[q] right-hand sides (None: none)."""
+
+    def __init__(self, M, N, nrhs, params: Params, exec_: Exec = None):
+        self.M, self.N = _i64(M), _i64(N)
+        self.nrhs = _i32(nrhs) if nrhs is not None else None
+        self.count = len(self.M)
+        h = ctypes.c_void_p()
+        rc = load().hqr_batch_create(self.count, _ptr(self.M), _ptr(self.N), _ptr(self.nrhs), ctypes.byref(params),
+                                     ctypes.byref(exec_) if exec_ is not None else None, ctypes.byref(h))
+        _check("hqr_batch_create", rc)
+        self.handle = h
+
+    def workspace_size(self) -> int:
+        n = ctypes.c_size_t()
+        _check("hqr_batch_workspace_size", load().hqr_batch_workspace_size(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def tasks(self):
+        """(task table as TASK_DTYPE, problem index of each task)."""
+        lib = load()
+        n = ctypes.c_int64()
+        _check("hqr_batch_num_tasks", lib.hqr_batch_num_tasks(self.handle, None, None, 0, ctypes.byref(n)))
+        t = np.zeros(n.value, dtype=TASK_DTYPE)
+        q = np.zeros(n.value, dtype=np.int32)
+        _check("hqr_batch_num_tasks", lib.hqr_batch_num_tasks(self.handle, _ptr(t), _ptr(q), n.value, ctypes.byref(n)))
+        return t, q
+
+    def bind(self, dA, lda, dB, ldb, dwork: int, work_bytes: int, stream: int) -> None:
+        self._keep = (_i64(dA).astype(np.uint64), _i64(lda),
+                      _i64(dB).astype(np.uint64) if dB is not None else None,
+                      _i64(ldb) if ldb is not None else None)
+        a, la, b, lb = self._keep
+        rc = load().hqr_batch_bind(self.handle, _ptr(a), _ptr(la), _ptr(b), _ptr(lb), ctypes.c_void_p(dwork),
+                                   work_bytes, ctypes.c_void_p(stream))
+        _check("hqr_batch_bind", rc)
+
+    def run(self, dwork: int, work_bytes: int, stream: int) -> None:
+        _check("hqr_batch_run", load().hqr_batch_run(self.handle, ctypes.c_void_p(dwork), work_bytes,
+                                                     ctypes.c_void_p(stream)))
+
+    def status(self, dwork: int, stream: int, timeout_s: float = 0.0):
+        """(status word, first zero diagonal index per problem or -1)."""
+        s = ctypes.c_int32()
+        fz = np.zeros(self.count, dtype=np.int32)
+        _check("hqr_batch_status", load().hqr_batch_status(self.handle, ctypes.c_void_p(dwork),
+                                                           ctypes.c_void_p(stream), timeout_s, ctypes.byref(s),
+                                                           _ptr(fz)))
+        return s.value, fz
+
+    def close(self) -> None:
+        if self.handle:
+            load().hqr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lstsq_batched_workspace_size(M, N, nrhs, params: Params) -> int:
+    m, n_ = _i64(M), _i64(N)
+    r = _i32(nrhs) if nrhs is not None else None
+    n = ctypes.c_size_t()
+    _check("hqr_lstsq_batched_workspace_size",
+           load().hqr_lstsq_batched_workspace_size(len(m), _ptr(m), _ptr(n_), _ptr(r), ctypes.byref(params),
+                                                   ctypes.byref(n)))
+    return n.value
+
+
+def lstsq_batched_ptr(dA, M, N, lda, dB, ldb, nrhs, params: Params, exec_: Exec, dwork: int, work_bytes: int,
+                      stream: int) -> None:
+    a = _i64(dA).astype(np.uint64)
+    m, n_, la = _i64(M), _i64(N), _i64(lda)
+    b = _i64(dB).astype(np.uint64) if dB is not None else None
+    lb = _i64(ldb) if ldb is not None else None
+    r = _i32(nrhs) if nrhs is not None else None
+    rc = load().hqr_lstsq_batched(len(m), _ptr(a), _ptr(m), _ptr(n_), _ptr(la), _ptr(b), _ptr(lb), _ptr(r),
+                                  ctypes.byref(params), ctypes.byref(exec_) if exec_ is not None else None,
+                                  ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(stream))
+    _check("hqr_lstsq_batched", rc)
 
 
 def release_plans() -> None:

@@ -14,13 +14,12 @@
 
 #include "../../include/hqr.h"
 #include "elim.hpp"
+#include "layout.hpp"
 #include "task.hpp"
 
 namespace hqr {
 namespace {
 
-constexpr int64_t kDefaultSpinLimit = 20000000;  // polls of one counter (tens of seconds)
-constexpr int kCtrlWords = 64;                    // cursor, status, spare
 
 // order: 0/1 for factorization plans, 2 + trans for apply plans (nbc = B
 // blocks); last_a / nrhs: the active chunks of the factorization (ColumnChunks).
@@ -78,41 +77,6 @@ int32_t* trace_buffer() {
   return g_trace;
 }
 std::map<PlanKey, std::unique_ptr<DevicePlan>> g_plans;
-
-// Dependency counters per tile: one per 64-column sub-chunk (an update task
-// covers two of them, a panel task publishes them one block at a time).
-int chunk_cols(int nb) { (void)nb; return 64; }
-int chunks_for(int nb) { return nb / chunk_cols(nb); }
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-struct Layout {
-  int32_t mt, nt, nrt, chunks, last_a;  // nrt: tile columns of right-hand sides (hqr_lstsq)
-  size_t ctrl, cnt, tg, tk, tiles, total;
-};
-
-// Workspace: control words, dependency counters, the T factors of the panel
-// kernels (one nb x 16 block column per tile and kind) and the
-// tile-contiguous copy of the matrix the factorization works on, followed
-// (hqr_lstsq) by nrhs right-hand-side columns as further tile columns.
-Layout layout_for(int64_t M, int64_t N, const hqr_params& p, int64_t nrhs = 0) {
-  Layout L{};
-  L.mt = (int32_t)((M + p.nb - 1) / p.nb);
-  L.nt = (int32_t)((N + p.nb - 1) / p.nb);
-  L.nrt = (int32_t)((nrhs + p.nb - 1) / p.nb);
-  L.chunks = chunks_for(p.nb);
-  const int cw = chunk_cols(p.nb);
-  L.last_a = (int32_t)((N - (int64_t)(L.nt - 1) * p.nb + cw - 1) / cw);
-  const size_t tiles = (size_t)L.mt * L.nt, all = (size_t)L.mt * (L.nt + L.nrt);
-  size_t off = 0;
-  L.ctrl = off; off = align256(off + kCtrlWords * sizeof(int32_t));
-  L.cnt = off; off = align256(off + all * L.chunks * sizeof(int32_t));
-  L.tg = off; off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
-  L.tk = off; off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
-  L.tiles = off; off = align256(off + all * (size_t)p.nb * p.nb * sizeof(double));
-  L.total = off;
-  return L;
-}
 
 // Cached device plan: order 0/1 = factorization, 2 + trans = apply on nbc
 // blocks of B.

@@ -443,6 +443,7 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
 
   if (order == 1) {
     plan.dev.swap(dev);
+    plan.prio.swap(prio);
     return 0;
   }
   // list schedule: repeatedly take the ready task with the longest remaining path
@@ -453,10 +454,12 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
   for (int64_t i = 0; i < nd; ++i)
     if (indeg[i] == 0) ready.push({prio[i], -i});
   plan.dev.reserve(nd);
+  plan.prio.reserve(nd);
   while (!ready.empty()) {
     const int64_t i = -ready.top().second;
     ready.pop();
     plan.dev.push_back(dev[i]);
+    plan.prio.push_back(prio[i]);
     for (int64_t q = nsucc[i]; q < nsucc[i + 1]; ++q)
       if (--indeg[succ[q]] == 0) ready.push({prio[succ[q]], -succ[q]});
   }

@@ -76,6 +76,7 @@ struct Plan {
   int32_t mt = 0, nt = 0, nb = 0, chunks = 1;
   std::vector<Elim> list;
   std::vector<DevTask> dev;  // in dispatch order
+  std::vector<int64_t> prio; // dispatch priority of each task of dev (factorization plans)
   hqr_dag_info info{};
 };
 

@@ -951,18 +951,36 @@ __device__ __noinline__ void apply_task(const LaunchArgs& a, const DevTask& task
                                  b_block(a, NB, task.row, task.j), NB);
 }
 
+// Points the per-problem fields of `la` (tiles, T factors, counters, tile
+// grid) at the problem of task t of a batched launch.
+__device__ __forceinline__ void bind_problem(LaunchArgs& la, const LaunchArgs& a, int t) {
+  const ProbDesc* d = a.probs + a.task_prob[t];
+  char* w = (char*)a.ctrl;
+  la.A = (double*)(w + d->tiles);
+  la.Tg = (double*)(w + d->tg);
+  la.Tk = (double*)(w + d->tk);
+  la.cnt = (int32_t*)(w + d->cnt);
+  la.mt = d->mt;
+  la.nt = d->nt;
+  la.cnt_cols = d->nt + d->nrt;
+}
+
 // Persistent scheduler.  Workgroups take task indices from a global cursor
 // in dispatch order (a topological order of the task graph), wait until the
 // dependency counters of the tiles the task touches reach the versions in
 // the task record, run it, and bump the counters of the tiles it wrote.
 // Every task a workgroup waits for was taken earlier by a running
-// workgroup, so the wait always ends.
-template <int NB>
-__global__ __launch_bounds__(NT, 1) void persistent_kernel(LaunchArgs a) {
+// workgroup, so the wait always ends.  BATCH: the tasks of many independent
+// problems share the cursor (each task names its problem).
+template <int NB, bool BATCH>
+__global__ __launch_bounds__(NT, 1) void persistent_kernel(LaunchArgs args) {
+  LaunchArgs la = args;
   for (;;) {
-    const int t = take_task<NB>(a);
+    const int t = take_task<NB>(args);
     if (t < 0) break;
-    const DevTask task = a.tasks[t];
+    const DevTask task = args.tasks[t];
+    if (BATCH) bind_problem(la, args, t);
+    const LaunchArgs& a = BATCH ? la : args;
     if (!wait_task<NB>(a, t, task)) break;
     int ok = 1;
     if (a.B) {
@@ -1008,18 +1026,41 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
 // B).  `in` fills the blocks and zeroes the padding beyond M and N; `out`
 // copies the M x N part back.  One thread per element of the padded matrix,
 // rows fastest.
+__device__ __forceinline__ void tile_copy_elem(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb,
+                                               int tw, int mt, int64_t x, int in) {
+  const int64_t Mp = (int64_t)mt * nb;
+  const int64_t r = x % Mp, c = x / Mp;
+  const int64_t i = r / nb, j = c / tw;
+  double* t = At + ((j * mt + i) * tw + (c - j * tw)) * nb + (r - i * nb);
+  const bool inside = r < M && c < N;
+  if (in)
+    *t = inside ? A[r + c * lda] : 0.0;
+  else if (inside)
+    A[r + c * lda] = *t;
+}
+
 __global__ void tile_copy_kernel(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int tw, int mt,
                                  int nt, int in) {
-  const int64_t Mp = (int64_t)mt * nb, total = Mp * (int64_t)nt * tw;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = x % Mp, c = x / Mp;
-    const int64_t i = r / nb, j = c / tw;
-    double* t = At + ((j * mt + i) * tw + (c - j * tw)) * nb + (r - i * nb);
-    const bool inside = r < M && c < N;
-    if (in)
-      *t = inside ? A[r + c * lda] : 0.0;
-    else if (inside)
-      A[r + c * lda] = *t;
+  const int64_t total = (int64_t)mt * nb * (int64_t)nt * tw;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x)
+    tile_copy_elem(A, lda, At, M, N, nb, tw, mt, x, in);
+}
+
+// Batched copy: workgroup row blockIdx.y serves problem blockIdx.y, first
+// its matrix (nt tile columns), then its right-hand sides (nrt tile columns
+// appended to the same tile array).
+__global__ void copy_batched_kernel(const ProbDesc* descs, char* w, int nb, int in) {
+  const ProbDesc* d = descs + blockIdx.y;
+  double* At = (double*)(w + d->tiles);
+  double* Bt = At + (int64_t)d->mt * d->nt * nb * nb;
+  const int64_t Mp = (int64_t)d->mt * nb;
+  const int64_t ta = Mp * d->nt * nb, tb = d->nrhs > 0 ? Mp * d->nrt * nb : 0;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < ta + tb;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    if (x < ta)
+      tile_copy_elem(d->A, d->lda, At, d->M, d->N, nb, nb, d->mt, x, in);
+    else
+      tile_copy_elem(d->B, d->ldb, Bt, d->M, d->nrhs, nb, nb, d->mt, x - ta, in);
   }
 }
 
@@ -1034,13 +1075,12 @@ __global__ void tile_copy_kernel(double* A, int64_t lda, double* At, int64_t M, 
 //   z -> R_ii^{-1} z, 16 rows at a time: lanes 0..15 of wave 0 solve the
 //   16 x 16 diagonal block (lane = column), the rows above subtract it.
 // A zero diagonal entry R_jj is recorded in ctrl (status HQR_ERR_SINGULAR,
-// ctrl[6] = max over such j of N - j).
+// *info = max over such j of N - j; nword, when not null, receives N).
 template <int NB>
-__global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const double* R, double* Y, int cpt, int32_t* ctrl,
-                                                           int64_t N, int mt, int nt, int i, int groups) {
+__device__ void trsm_tile_row(const double* R, double* Y, int cpt, int32_t* ctrl, int32_t* info, int32_t* nword,
+                              int64_t N, int mt, int nt, int i, int blk, int grp) {
   double* xs = hqr_lds;  // x_j or z of this tile row: NB rows x 16 columns, stride 17 (dynamic LDS)
   const int r = threadIdx.x;
-  const int blk = blockIdx.x / groups, grp = blockIdx.x % groups;
   const int64_t row0 = (int64_t)i * NB;
   const int nv = (int)((N - row0) < NB ? (N - row0) : NB);  // rows of this tile row inside N
   // Y: tile columns of 64 cpt columns; block blk = chunk blk % cpt of tile column blk / cpt
@@ -1083,8 +1123,8 @@ __global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const double* R, doub
           int32_t none = 0;
           __hip_atomic_compare_exchange_strong(&ctrl[1], &none, (int32_t)HQR_ERR_SINGULAR, __ATOMIC_RELAXED,
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_fetch_max(&ctrl[6], (int32_t)(N - (row0 + rr)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&ctrl[7], (int32_t)N, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_max(info, (int32_t)(N - (row0 + rr)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (nword) __hip_atomic_store(nword, (int32_t)N, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         xs[rr * 17 + c] = t / d;
       }
@@ -1103,6 +1143,34 @@ __global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const double* R, doub
   if (r < nv) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) Yb[(int64_t)i * rstride + r + (int64_t)c * NB] = xs[r * 17 + c];
+  }
+}
+
+// Tile row i of one problem; workgroup x = (64-column block, group of 16).
+// A zero diagonal entry sets ctrl[6] = max(N - j) and ctrl[7] = N.
+template <int NB>
+__global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const double* R, double* Y, int cpt, int32_t* ctrl,
+                                                           int64_t N, int mt, int nt, int i, int groups) {
+  trsm_tile_row<NB>(R, Y, cpt, ctrl, &ctrl[6], &ctrl[7], N, mt, nt, i, blockIdx.x / groups, blockIdx.x % groups);
+}
+
+// Every tile row of every problem of a batch in one launch: workgroup
+// (x, q) solves one group of 16 right-hand-side columns of problem q from
+// the last tile row up; it reads back only the rows of x it wrote itself.
+template <int NB>
+__global__ __launch_bounds__(NB) void trsm_batched_kernel(const ProbDesc* descs, char* w, int32_t* ctrl,
+                                                          int32_t* info) {
+  const ProbDesc* d = descs + blockIdx.y;
+  const int nrhs = d->nrhs;
+  if (nrhs == 0) return;
+  const int nbc = (nrhs + 63) / 64, groups = nbc > 1 ? 4 : (nrhs + 15) / 16;
+  if ((int)blockIdx.x >= nbc * groups) return;
+  const double* R = (const double*)(w + d->tiles);
+  double* Y = (double*)(w + d->tiles) + (int64_t)d->mt * d->nt * NB * NB;
+  for (int i = d->nt - 1; i >= 0; --i) {
+    trsm_tile_row<NB>(R, Y, NB / 64, ctrl, info + blockIdx.y, nullptr, d->N, d->mt, d->nt, i,
+                      (int)blockIdx.x / groups, (int)blockIdx.x % groups);
+    __syncthreads();  // the rows of x just stored are read by the next tile rows
   }
 }
 
@@ -1162,12 +1230,32 @@ int launch_trsm(int nb, const double* R, double* Y, int cpt, int32_t* ctrl, int6
   return 0;
 }
 
+int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, void* stream) {
+  if (count <= 0) return 0;
+  hipLaunchKernelGGL(copy_batched_kernel, dim3(256, count), dim3(256), 0, (hipStream_t)stream, d, w, nb, in ? 1 : 0);
+  return record_hip(hipGetLastError(), "copy_batched_kernel launch");
+}
+
+int launch_trsm_batched(int nb, const ProbDesc* d, char* w, int32_t* ctrl, int32_t* info, int count, int gmax,
+                        void* stream) {
+  if (count <= 0 || gmax <= 0) return 0;
+  const dim3 grid(gmax, count), block(nb);
+  const size_t lds = (size_t)nb * 17 * sizeof(double);
+  hipStream_t s = (hipStream_t)stream;
+  switch (nb) {
+    case 64: hipLaunchKernelGGL(trsm_batched_kernel<64>, grid, block, lds, s, d, w, ctrl, info); break;
+    case 128: hipLaunchKernelGGL(trsm_batched_kernel<128>, grid, block, lds, s, d, w, ctrl, info); break;
+    default: hipLaunchKernelGGL(trsm_batched_kernel<256>, grid, block, lds, s, d, w, ctrl, info); break;
+  }
+  return record_hip(hipGetLastError(), "trsm_batched_kernel launch");
+}
+
 template <int NB>
 static int occupancy_workers() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_kernel<NB>, NT, sizeof(Smem<NB>)) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_kernel<NB, false>, NT, sizeof(Smem<NB>)) != hipSuccess ||
       per < 1)
     per = 1;
   return cus * per;
@@ -1184,11 +1272,21 @@ int default_workers(int nb) {
 int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream) {
   if (workers < 1) workers = 1;
   hipStream_t s = (hipStream_t)stream;
-  switch (nb) {
-    case 64: hipLaunchKernelGGL(persistent_kernel<64>, dim3(workers), dim3(NT), sizeof(Smem<64>), s, a); break;
-    case 128: hipLaunchKernelGGL(persistent_kernel<128>, dim3(workers), dim3(NT), sizeof(Smem<128>), s, a); break;
-    case 256: hipLaunchKernelGGL(persistent_kernel<256>, dim3(workers), dim3(NT), sizeof(Smem<256>), s, a); break;
-    default: return HQR_ERR_INTERNAL;
+  const dim3 g(workers), b(NT);
+  if (a.probs) {
+    switch (nb) {
+      case 64: hipLaunchKernelGGL((persistent_kernel<64, true>), g, b, sizeof(Smem<64>), s, a); break;
+      case 128: hipLaunchKernelGGL((persistent_kernel<128, true>), g, b, sizeof(Smem<128>), s, a); break;
+      case 256: hipLaunchKernelGGL((persistent_kernel<256, true>), g, b, sizeof(Smem<256>), s, a); break;
+      default: return HQR_ERR_INTERNAL;
+    }
+  } else {
+    switch (nb) {
+      case 64: hipLaunchKernelGGL((persistent_kernel<64, false>), g, b, sizeof(Smem<64>), s, a); break;
+      case 128: hipLaunchKernelGGL((persistent_kernel<128, false>), g, b, sizeof(Smem<128>), s, a); break;
+      case 256: hipLaunchKernelGGL((persistent_kernel<256, false>), g, b, sizeof(Smem<256>), s, a); break;
+      default: return HQR_ERR_INTERNAL;
+    }
   }
   return record_hip(hipGetLastError(), "persistent_kernel launch");
 }

@@ -10,6 +10,22 @@
 
 namespace hqr {
 
+// One problem of a batched launch (hqr_batch_*).  Offsets are bytes from the
+// start of the batch workspace; the problem's tiles, T factors and
+// dependency counters are laid out there exactly as for a single
+// factorization of the same shape.
+struct ProbDesc {
+  double* A;         // caller's M x N matrix (column-major, lda): copied in, R and V copied back
+  double* B;         // caller's M x nrhs right-hand sides (ldb), null when nrhs = 0
+  int64_t lda, ldb;
+  int64_t M, N;
+  int64_t tiles;     // tile-contiguous copy of A followed by the right-hand-side tile columns
+  int64_t tg, tk;    // T factors (GEQRT, TSQRT/TTQRT)
+  int64_t cnt;       // dependency counters, mt * (nt + nrt) * chunks
+  int32_t nrhs, mt, nt, nrt;
+};
+static_assert(sizeof(ProbDesc) == 96, "problem descriptor layout");
+
 struct LaunchArgs {
   double* A;          // tile-contiguous matrix: tile (r, c) at (c * mt + r) * nb * nb
   int64_t lda;        // leading dimension inside a tile (= nb)
@@ -27,6 +43,11 @@ struct LaunchArgs {
   int32_t mt, nt, chunks;
   int32_t cnt_cols;   // columns of the counter grid (nt, or the number of B blocks)
   int32_t trans;      // apply: 1 = Q^T, 0 = Q
+  // batched launch: problem descriptors and the problem of every task (null
+  // for a single problem); offsets in the descriptors are relative to ctrl,
+  // the start of the workspace
+  const ProbDesc* probs;
+  const int32_t* task_prob;
 };
 
 // Progress phases published per workgroup when tracing is on.
@@ -57,6 +78,15 @@ int launch_trsm(int nb, const double* R, double* Y, int cpt, int32_t* ctrl, int6
 // HQR_ERR_HIP on failure, 0 on success.
 int record_hip(hipError_t e, const char* where);
 const char* last_error();
+
+// Batched launches (one launch for `count` problems described by the
+// device array `d`, offsets relative to the workspace base `w`): copy the
+// matrices and right-hand sides into their tiles (in) or A and B back out;
+// back substitution of every problem's right-hand sides (first zero
+// diagonal entry j of problem q recorded as info[q] = max(N - j)).
+int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, void* stream);
+int launch_trsm_batched(int nb, const ProbDesc* d, char* w, int32_t* ctrl, int32_t* info, int count, int gmax,
+                        void* stream);
 
 // Workgroups that fit on the device at once (per CU occupancy x CUs).
 int default_workers(int nb);

@@ -65,3 +65,23 @@ def graded_device(n: int, seed: int, smin: float = 1e-8, device="cuda"):
     # row-major V (U diag(sigma))^T is the column-major storage of U diag(sigma) V^T
     At = V @ (U * sigma).t()
     return At.t()
+
+
+def request_shapes(count: int, seed: int, mlo: int = 256, mhi: int = 16384, nlo: int = 32, nhi: int = 512):
+    """(m, n) int64 arrays of `count` request shapes, m >= n."""
+    rng = np.random.default_rng(seed)
+    m = np.zeros(count, dtype=np.int64)
+    n = np.zeros(count, dtype=np.int64)
+    for q in range(count):
+        while True:
+            mq = int(rng.integers(mlo, mhi + 1))
+            nq = int(rng.integers(nlo, nhi + 1))
+            if mq >= nq:
+                break
+        m[q], n[q] = mq, nq
+    return m, n
+
+
+def arrival_gaps(count: int, rate: float, seed: int) -> np.ndarray:
+    """Exponential inter-arrival times (seconds) of a Poisson stream."""
+    return np.random.default_rng(seed).exponential(1.0 / rate, count)
