@@ -10,6 +10,16 @@ Fibonacci high level, 8 virtual clusters).  Throughput is reported in GFLOP/s
 of the Householder count 2MN^2 - 2N^3/3 (the total weight of any elimination
 list, Section II of the paper), next to the FP64 matrix peak of MI355X.
 
+Next to the headline line it measures (keys "lstsq" and "serving"):
+* least squares of a 32768 x 2048 matrix with condition number 1e6 (one
+  hqr_lstsq: factorization with the right-hand side carried along, then back
+  substitution): solves per second;
+* continuous-batching serving of 4096 least-squares requests (rows uniform
+  in [256, 16384], columns uniform in [32, 512], one right-hand side,
+  Poisson arrivals at 0.8 of the measured saturated throughput, 8 GiB
+  workspace budget, tile size and tree autotuned on the first 64 requests):
+  solves per second and p50/p99 latency.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 Prints one JSON line.
 """
@@ -133,6 +143,101 @@ def run_workload(name, steps, warmup, device, keep_result=False):
     return out, result, host_sample
 
 
+def run_lstsq(device, M=32768, N=2048, seed=4, reps=5):
+    """FP64 least squares on the tall graded matrix (kappa = 1e6)."""
+    import torch
+
+    import paper_1110_1553_amd as h
+    from paper_1110_1553_amd import inputs
+
+    params = h.make_params(nb=256, p=4, a=4, low="greedy", high="fibonacci", domino=1)
+    A0 = h.colmajor(inputs.graded_tall_device(M, N, seed, 1e-6, device))
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 1)
+    xs = torch.randn((N, 1), generator=g, device=device, dtype=torch.float64)
+    b0 = h.colmajor(A0 @ xs + 1e-10 * torch.randn((M, 1), generator=g, device=device, dtype=torch.float64))
+    work = h.Workspace(M, N, params, device=device, nrhs=1)
+    stream = torch.cuda.current_stream(device)
+    A, b = A0.clone(), b0.clone()
+    times = []
+    for r in range(reps + 1):
+        A.copy_(A0)
+        b.copy_(b0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        h.lstsq(A, b, params, work=work, stream=stream, check=False)
+        e1.record(stream)
+        e1.synchronize()
+        if r > 0:
+            times.append(e0.elapsed_time(e1) / 1e3)
+    if h.status(work, stream) != 0:
+        raise RuntimeError("device status %d in the least-squares workload" % h.status(work, stream))
+    x = b[:N]
+    r_ = b0 - A0 @ x
+    # optimality of the computed solution: ||A^T r|| / (||A||^2 ||x||) is of the order of the unit roundoff
+    # for a backward-stable solver
+    nA = torch.linalg.matrix_norm(A0, 2).item()
+    opt = (A0.t() @ r_).norm().item() / (nA * nA * x.norm().item())
+    t = sum(times) / len(times)
+    out = {"workload": "FP64 least squares %dx%d, kappa 1e6, one right-hand side, nb=256 hierarchical tree" % (M, N),
+           "solves_per_s": 1.0 / t, "ms_per_solve": 1e3 * t,
+           "gflops": (qr_flops(M, N) + 4.0 * M * N) / t / 1e9,
+           "forward_error_vs_x_true": ((x - xs).norm() / xs.norm()).item(),
+           "normal_equations_residual": opt}
+    del A, b, A0, b0, work
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_serving(device, count=4096, budget_gib=8, seed=5, load=0.8, tune_sample=64):
+    """Continuous-batching serving of a Poisson stream of least-squares requests."""
+    import numpy as np
+    import torch
+
+    import paper_1110_1553_amd as h
+    from paper_1110_1553_amd import inputs, serve, tune
+
+    m, n = inputs.request_shapes(count, seed)
+    tuner = tune.Autotuner()
+    best, _ = tuner.tune_batch(list(zip(m[:tune_sample], n[:tune_sample])), [1] * tune_sample, device=device)
+    params = h.make_params(**best)
+    print("bench: serving params %s" % best, file=sys.stderr, flush=True)
+
+    def make_requests(arrivals):
+        reqs = []
+        for q in range(count):
+            A = inputs.gaussian_device(int(m[q]), int(n[q]), 100000 + q, device)
+            B = inputs.gaussian_device(int(m[q]), 1, 200000 + q, device)
+            reqs.append(serve.Request(q, A, B, float(arrivals[q])))
+        torch.cuda.synchronize(device)
+        return reqs
+
+    be = serve.GpuBackend(params, budget_gib << 30, max_inflight=2, device=device)
+    # saturated throughput: every request waiting at the start
+    reqs = make_requests(np.zeros(count))
+    sch = serve.Scheduler(be)
+    sch.run(reqs)
+    span = max(r.done for r in reqs)
+    sat = count / span
+    del reqs, sch
+    # Poisson arrivals at `load` times that rate
+    arrivals = np.cumsum(inputs.arrival_gaps(count, load * sat, seed + 1))
+    reqs = make_requests(arrivals)
+    sch = serve.Scheduler(be)
+    lat = sch.run(reqs)
+    bad = sum(1 for r in reqs if r.status != 0)
+    s = serve.summarize(lat, reqs, max(r.done for r in reqs))
+    flops = float(sum(qr_flops(int(a), int(b)) + 4.0 * a * b for a, b in zip(m, n)))
+    out = {"workload": "%d least-squares requests, rows U[256,16384], cols U[32,512], 1 rhs, Poisson arrivals" % count,
+           "params": best, "budget_GiB": budget_gib, "saturated_solves_per_s": sat,
+           "saturated_gflops": flops / span / 1e9, "arrival_rate_per_s": load * sat,
+           "solves_per_s": s["solves_per_s"], "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"],
+           "batches": len(sch.batches), "mean_batch": count / len(sch.batches), "failed": bad}
+    del reqs, sch, be
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(sample):
     """The oracle (unblocked Householder QR) on a bounded sample of the workload."""
     import numpy as np
@@ -158,6 +263,8 @@ def main():
     ap.add_argument("--secondary", default="tall-flat,tall-binary,square-greedy,square-flat",
                     help="comma-separated workloads also timed (1 step each after 1 warm-up); empty for none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", type=int, default=4096, help="requests in the serving trace (0: skip serving)")
+    ap.add_argument("--no-lstsq", action="store_true", help="skip the least-squares measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -176,6 +283,15 @@ def main():
         print("bench: %s %.3f ms/step" % (name, res["ms_per_step"]), file=sys.stderr, flush=True)
         secondary.append({k: res[k] for k in ("workload", "label", "ms_per_step", "gflops", "tflops_launch",
                                               "frac_peak")})
+    lstsq = None
+    if not args.no_lstsq:
+        lstsq = run_lstsq(device)
+        print("bench: lstsq %.3f ms/solve" % lstsq["ms_per_solve"], file=sys.stderr, flush=True)
+    serving = None
+    if args.serve > 0:
+        serving = run_serving(device, count=args.serve)
+        print("bench: serving %.0f solves/s p50 %.2f ms p99 %.2f ms" % (
+            serving["solves_per_s"], serving["p50_ms"], serving["p99_ms"]), file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline and host_sample is not None:
         cpu, _ = cpu_baseline(host_sample)
@@ -203,6 +319,8 @@ def main():
                      "launch_ms": round(1e3 * primary["launch_s"], 3)},
         "cpu_baseline": cpu,
         "secondary": secondary,
+        "lstsq": lstsq,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

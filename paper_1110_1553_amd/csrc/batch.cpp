@@ -18,11 +18,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <queue>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -326,15 +328,29 @@ int hqr_batch_status(const hqr_batch* b, const void* dwork, void* stream, double
   if (!b) return -1;
   if (!dwork) return -2;
   if (!status) return -5;
-  if (int rc = hqr_status_ex(dwork, stream, timeout_s, status, nullptr)) return rc;
-  if (!first_zero) return 0;
-  std::vector<int32_t> info(b->count, 0);
-  if (int rc = record_hip(hipMemcpy(info.data(), (const char*)dwork + b->off_info, info.size() * sizeof(int32_t),
-                                    hipMemcpyDeviceToHost),
-                          "hipMemcpy(batch info)"))
+  hipStream_t s = (hipStream_t)stream;
+  if (timeout_s <= 0.0) timeout_s = 300.0;
+  // bounded wait for `stream`, then reads through that stream only (the
+  // batch may have finished while later work still runs on another stream)
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    hipError_t e = hipStreamQuery(s);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) return record_hip(e, "hipStreamQuery");
+    if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > timeout_s)
+      return HQR_ERR_TIMEOUT;
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  std::vector<int32_t> words(b->off_info / sizeof(int32_t) + b->count, 0);
+  if (int rc = record_hip(hipMemcpyAsync(words.data(), dwork, words.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+                          "hipMemcpyAsync(batch status)"))
     return rc;
-  for (int32_t q = 0; q < b->count; ++q)
-    first_zero[q] = info[q] > 0 ? (int32_t)(b->N[q] - info[q]) : -1;
+  if (int rc = record_hip(hipStreamSynchronize(s), "hipStreamSynchronize(batch status)")) return rc;
+  *status = words[1];
+  if (first_zero) {
+    const int32_t* info = words.data() + b->off_info / sizeof(int32_t);
+    for (int32_t q = 0; q < b->count; ++q) first_zero[q] = info[q] > 0 ? (int32_t)(b->N[q] - info[q]) : -1;
+  }
   return 0;
 }
 

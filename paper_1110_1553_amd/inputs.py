@@ -85,3 +85,24 @@ def request_shapes(count: int, seed: int, mlo: int = 256, mhi: int = 16384, nlo:
 def arrival_gaps(count: int, rate: float, seed: int) -> np.ndarray:
     """Exponential inter-arrival times (seconds) of a Poisson stream."""
     return np.random.default_rng(seed).exponential(1.0 / rate, count)
+
+
+def graded_tall_device(M: int, N: int, seed: int, smin: float = 1e-6, device="cuda"):
+    """M x N (M >= N) column-major U diag(sigma) V^T, condition number 1/smin."""
+    import math
+
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    cols = torch.randperm(M, generator=g, device=device)[:N].to(torch.float64)
+    signs = torch.randint(0, 2, (M,), generator=g, device=device).to(torch.float64) * 2.0 - 1.0
+    i = torch.arange(M, device=device, dtype=torch.float64) + 0.5
+    # orthonormal DCT-II basis vectors: c_j(i) = s_j cos(pi (i + 1/2) j / M), s_0 = sqrt(1/M), s_j = sqrt(2/M)
+    scale = torch.where(cols == 0, torch.full_like(cols, math.sqrt(1.0 / M)), torch.full_like(cols, math.sqrt(2.0 / M)))
+    U = torch.cos(math.pi * i[:, None] * cols[None, :] / M) * scale[None, :] * signs[:, None]
+    S = torch.randn((N, N), generator=g, device=device, dtype=torch.float64) * (1.5 / (2.0 * N) ** 0.5)
+    V = torch.linalg.matrix_exp(S - S.t())
+    sigma = torch.logspace(0.0, float(np.log10(smin)), N, device=device, dtype=torch.float64)
+    At = V @ (U * sigma).t()  # row-major N x M = column-major M x N
+    return At.t()

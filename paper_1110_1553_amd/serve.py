@@ -1,0 +1,217 @@
+"""Continuous-batching least-squares serving on one GPU.
+
+Requests (A_q: M_q x N_q, b_q: M_q x nrhs_q, both already in device memory)
+arrive over time and wait in a FIFO queue.  Whenever fewer than
+``max_inflight`` batches are on the GPU and requests are waiting, the
+scheduler admits requests from the head of the queue while the batch
+workspace still fits in one slot of the HBM budget (the budget is split into
+``max_inflight`` workspace slots, allocated once), plans the batch on the
+host and launches it as one batched launch (copy-in, one persistent launch
+over the union of the task graphs, back substitution, copy-out).  Batches
+run in order on one stream, so a batch admitted while another runs starts
+the moment the GPU is free.  A request completes with the end event of its
+batch; its latency is that time minus its arrival time.
+
+A request's results do not depend on the batch it was served in: each
+problem of a batched launch runs the same tasks in the same per-tile order
+as a launch of that problem alone, so they are bitwise identical.
+
+The scheduling logic is separate from the GPU backend (``GpuBackend``) so
+that it can be exercised with a simulated backend.
+"""
+import collections
+import time
+
+import numpy as np
+
+from . import _lib
+
+
+class GpuBackend:
+    """Launches batches through hqr_batch_* on one stream, with workspace
+    slots carved out of one preallocated device buffer."""
+
+    def __init__(self, params, budget_bytes, max_inflight=2, device="cuda", exec_=None, stream=None):
+        import torch
+
+        self.params = params
+        self.exec_ = exec_ if exec_ is not None else _lib.make_exec()
+        self.device = torch.device(device)
+        # both streams are created by torch (non-blocking with respect to the
+        # null stream): the status of a finished batch is read on `side`
+        # while the next batch still runs on `stream`
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.side = torch.cuda.Stream(self.device)
+        self.slots = max_inflight
+        self.slot_bytes = (int(budget_bytes) // max_inflight) & ~255
+        self.pool = torch.empty(self.slot_bytes * max_inflight, dtype=torch.uint8, device=self.device)
+        self.free = list(range(max_inflight))
+        self._ws = {}
+        self.t0_event = None
+
+    # -- sizes -------------------------------------------------------------
+    def request_bytes(self, M, N, nrhs):
+        """Workspace estimate of one request inside a batch (its tiles, T
+        factors and counters, plus room for its task records)."""
+        key = (int(M), int(N), int(nrhs))
+        b = self._ws.get(key)
+        if b is None:
+            nb = self.params.nb
+            mt, nt, nrt = -(-M // nb), -(-N // nb), -(-nrhs // nb)
+            tasks = mt * nt * (nt + nrt) * 4 + 64  # above the update and panel task count of any tree
+            b = _lib.lstsq_workspace_size(M, N, nrhs, self.params) if nrhs > 0 else _lib.workspace_size(M, N, self.params)
+            b += tasks * 28 + 512
+            self._ws[key] = b
+        return b
+
+    # -- clock ---------------------------------------------------------------
+    def start_clock(self):
+        import torch
+
+        self.t0_event = torch.cuda.Event(enable_timing=True)
+        self.t0_event.record(self.stream)
+        self.t0_host = time.perf_counter()
+
+    def now(self):
+        return time.perf_counter() - self.t0_host
+
+    def sleep(self, dt):
+        time.sleep(dt)
+
+    # -- batches -------------------------------------------------------------
+    def launch(self, reqs):
+        """Plans, binds and launches the batch; returns a handle, or None
+        when its workspace exceeds a slot (the caller shrinks the batch)."""
+        import torch
+
+        M = [r.A.shape[0] for r in reqs]
+        N = [r.A.shape[1] for r in reqs]
+        nrhs = [r.B.shape[1] for r in reqs]
+        batch = _lib.Batch(M, N, nrhs, self.params, self.exec_)
+        need = batch.workspace_size()
+        if need > self.slot_bytes:
+            batch.close()
+            return None
+        slot = self.free.pop(0)
+        base = self.pool.data_ptr() + slot * self.slot_bytes
+        batch.bind([r.A.data_ptr() for r in reqs], [max(r.A.stride(1), r.A.shape[0]) for r in reqs],
+                   [r.B.data_ptr() for r in reqs], [max(r.B.stride(1), r.B.shape[0]) for r in reqs],
+                   base, self.slot_bytes, self.stream.cuda_stream)
+        batch.run(base, self.slot_bytes, self.stream.cuda_stream)
+        end = torch.cuda.Event(enable_timing=True)
+        end.record(self.stream)
+        return {"batch": batch, "slot": slot, "base": base, "end": end}
+
+    def done(self, h):
+        """Completion time (seconds since start_clock) or None if running."""
+        if not h["end"].query():
+            return None
+        t = self.t0_event.elapsed_time(h["end"]) / 1e3
+        self.side.wait_event(h["end"])
+        st, first_zero = h["batch"].status(h["base"], self.side.cuda_stream)
+        h["status"], h["first_zero"] = st, first_zero
+        h["batch"].close()
+        self.free.append(h["slot"])
+        return t
+
+
+class Request:
+    __slots__ = ("rid", "A", "B", "M", "N", "nrhs", "arrival", "done", "status", "first_zero")
+
+    def __init__(self, rid, A, B, arrival):
+        self.rid, self.A, self.B, self.arrival = rid, A, B, arrival
+        self.M, self.N = A.shape
+        self.nrhs = B.shape[1]
+        self.done = None
+        self.status = None
+        self.first_zero = None
+
+
+class Scheduler:
+    """FIFO admission under a per-slot byte budget and continuous batching
+    over a backend with ``backend.slots`` workspace slots (at most that many
+    batches in flight)."""
+
+    def __init__(self, backend, max_batch=4096, poll_s=20e-6):
+        self.backend = backend
+        self.max_inflight = backend.slots
+        self.max_batch = max_batch
+        self.poll_s = poll_s
+        self.batches = []
+
+    def admit(self, queue):
+        """Requests for the next batch: the longest FIFO prefix whose
+        estimated workspace fits a slot (at least the head)."""
+        out, used = [], 0
+        cap = self.backend.slot_bytes
+        while queue and len(out) < self.max_batch:
+            r = queue[0]
+            b = self.backend.request_bytes(r.M, r.N, r.nrhs)
+            if out and used + b > cap:
+                break
+            out.append(queue.popleft())
+            used += b
+        return out
+
+    def run(self, requests):
+        """Serves `requests` (sorted by arrival, seconds from the start) in
+        real time; returns the per-request latencies (seconds)."""
+        be = self.backend
+        queue = collections.deque()
+        inflight = []
+        nxt, finished = 0, 0
+        n = len(requests)
+        be.start_clock()
+        while finished < n:
+            now = be.now()
+            while nxt < n and requests[nxt].arrival <= now:
+                queue.append(requests[nxt])
+                nxt += 1
+            # retire finished batches (in launch order)
+            while inflight:
+                t = be.done(inflight[0]["h"])
+                if t is None:
+                    break
+                b = inflight.pop(0)
+                fz = b["h"].get("first_zero")
+                for q, r in enumerate(b["reqs"]):
+                    r.done = t
+                    r.status = b["h"].get("status", 0)
+                    r.first_zero = int(fz[q]) if fz is not None else -1
+                finished += len(b["reqs"])
+                b["t_done"] = t
+            if queue and len(inflight) < self.max_inflight:
+                reqs = self.admit(queue)
+                h = be.launch(reqs)
+                while h is None and len(reqs) > 1:  # the estimate was short: give back the tail
+                    half = len(reqs) // 2
+                    for r in reversed(reqs[half:]):
+                        queue.appendleft(r)
+                    reqs = reqs[:half]
+                    h = be.launch(reqs)
+                if h is None:
+                    raise RuntimeError("request %d does not fit a workspace slot" % reqs[0].rid)
+                rec = {"reqs": reqs, "h": h, "t_launch": be.now()}
+                inflight.append(rec)
+                self.batches.append(rec)
+                continue
+            if not inflight and not queue and nxt < n:
+                wait = requests[nxt].arrival - be.now()
+                if wait > 0:
+                    be.sleep(min(wait, 1e-3))
+            elif inflight:
+                be.sleep(self.poll_s)
+        return np.array([r.done - r.arrival for r in requests])
+
+
+def summarize(latencies, requests, span_s):
+    lat = np.asarray(latencies)
+    return {
+        "requests": len(requests),
+        "solves_per_s": len(requests) / span_s,
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_ms": float(lat.mean() * 1e3),
+        "max_ms": float(lat.max() * 1e3),
+        "span_s": span_s,
+    }
