@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix
 
 # HBM bytes per launch of persistent_kernel<256> from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE), each scaled by what the counter reads for the
@@ -70,6 +71,9 @@ WORKLOADS = {
                         label="tall-skinny FP64 QR 131072x2048, nb=256, BinaryTree with TT kernels"),
     "square-greedy": dict(M=16384, N=16384, seed=3, gen="graded", params=dict(nb=256, p=1, a=1, low="greedy"),
                           label="square FP64 QR 16384^2, sigma logspaced 1..1e-8, nb=256, Greedy with TT kernels"),
+    "tall-hqr-f32": dict(M=131072, N=2048, seed=2, gen="gaussian", params=HQR, dtype="f32",
+                         label="tall-skinny FP32 QR 131072x2048 iid N(0,1) (FP32 tile kernels), nb=256, hierarchical "
+                               "tree (TS domains a=4, Greedy low, domino coupling, Fibonacci high, p=8)"),
     "square-flat": dict(M=16384, N=16384, seed=3, gen="graded", params=dict(nb=256, p=1, a=64, low="flat"),
                         label="square FP64 QR 16384^2, sigma logspaced 1..1e-8, nb=256, FlatTree with TS kernels"),
 }
@@ -96,7 +100,10 @@ def run_workload(name, steps, warmup, device, keep_result=False):
     M, N = w["M"], w["N"]
     params = h.make_params(**w["params"])
     pristine = h.colmajor(make_input(w, device))
-    work = h.Workspace(M, N, params, device=device)
+    f32 = w.get("dtype") == "f32"
+    if f32:
+        pristine = h.colmajor(pristine.to(torch.float32))
+    work = h.Workspace(M, N, params, device=device, f32=f32)
     stream = torch.cuda.current_stream(device)
     # warm-up: builds and uploads the task plan, loads the code object
     scratch = torch.empty_like(pristine)
@@ -133,7 +140,7 @@ def run_workload(name, steps, warmup, device, keep_result=False):
         "launch_s_max": max(ev),
         "tflops_launch": fl / (sum(ev) / len(ev)) / 1e12,
     }
-    out["frac_peak"] = out["tflops_launch"] / PEAK_FP64_TFLOPS
+    out["frac_peak"] = out["tflops_launch"] / (PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS)
     result = copies[0] if keep_result else None
     host_sample = None
     if keep_result:
@@ -260,7 +267,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tall-hqr", choices=sorted(WORKLOADS))
-    ap.add_argument("--secondary", default="tall-flat,tall-binary,square-greedy,square-flat",
+    ap.add_argument("--secondary", default="tall-flat,tall-binary,square-greedy,square-flat,tall-hqr-f32",
                     help="comma-separated workloads also timed (1 step each after 1 warm-up); empty for none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", type=int, default=4096, help="requests in the serving trace (0: skip serving)")
@@ -297,6 +304,8 @@ def main():
         cpu, _ = cpu_baseline(host_sample)
         print("bench: cpu baseline %s" % cpu["sample"], file=sys.stderr, flush=True)
     w = WORKLOADS[args.workload]
+    f32 = w.get("dtype") == "f32"
+    peak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
     line = {
         "metric": METRIC,
         "value": round(primary["gflops"], 1),
@@ -308,14 +317,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if f32 else "f64",
         "data": "synthetic",
         "config": {"workload": w["label"], "M": w["M"], "N": w["N"], "tree": w["params"],
-                   "frac_fp64_peak": round(primary["frac_peak"], 4)},
-        "roofline": {"bound": "mfma", "achieved": round(primary["tflops_launch"], 3), "peak": PEAK_FP64_TFLOPS,
+                   "frac_peak": round(primary["frac_peak"], 4)},
+        "roofline": {"bound": "mfma", "achieved": round(primary["tflops_launch"], 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(primary["frac_peak"], 4),
                      "traffic": traffic_for(args.workload), "traffic_unit": "bytes per launch (HBM read + write)",
-                     "kernel": "persistent_kernel<256> (all tile kernels of one factorization)",
+                     "kernel": "persistent_kernel<%s, 256> (all tile kernels of one factorization)" % (
+                         "float" if f32 else "double"),
                      "launch_ms": round(1e3 * primary["launch_s"], 3)},
         "cpu_baseline": cpu,
         "secondary": secondary,

@@ -199,6 +199,20 @@ int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* b
 int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params,
                const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
 
+/* ---- Single precision ----
+ *
+ * The same tiled algorithm, elimination lists and persistent launch with
+ * FP32 tiles and FP32 arithmetic (tile kernels on v_mfma_f32_16x16x4f32).
+ * Workspace bytes of hqr_factor_f32 (tiles and T factors in float).  Errors
+ * as hqr_workspace_size. */
+int hqr_workspace_size_f32(int64_t M, int64_t N, const hqr_params* params, size_t* bytes);
+
+/* QR of the column-major float matrix dA (M x N, lda >= M) in place, as
+ * hqr_factor: R in the upper triangle, the Householder vectors below it,
+ * the T factors (float) in dwork.  Errors as hqr_factor. */
+int hqr_factor_f32(float* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params, const hqr_exec* exec,
+                   void* dwork, size_t work_bytes, void* stream);
+
 /* Bytes of the second workspace that hqr_apply_qt and hqr_apply_q need for a
  * right-hand side B of M rows and nrhs columns: a
  * status word, one dependency counter per block and B in blocks of nb rows x

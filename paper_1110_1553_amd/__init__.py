@@ -33,12 +33,16 @@ def colmajor(t):
 
 class Workspace:
     """Device workspace for :func:`factor` (a torch uint8 buffer); with
-    ``nrhs`` > 0 the larger one of :func:`lstsq`."""
+    ``nrhs`` > 0 the larger one of :func:`lstsq`; with ``f32`` the one of a
+    float32 factorization."""
 
-    def __init__(self, M, N, params, device="cuda", nrhs=0):
+    def __init__(self, M, N, params, device="cuda", nrhs=0, f32=False):
         import torch
 
-        self.bytes = lstsq_workspace_size(M, N, nrhs, params) if nrhs > 0 else workspace_size(M, N, params)
+        if f32:
+            self.bytes = _lib.workspace_size_f32(M, N, params)
+        else:
+            self.bytes = lstsq_workspace_size(M, N, nrhs, params) if nrhs > 0 else workspace_size(M, N, params)
         self.buf = torch.empty(self.bytes, dtype=torch.uint8, device=device)
 
     @property
@@ -81,20 +85,23 @@ def _device_status(work, s, what, timeout_s=0.0):
 
 
 def factor(A, params, exec_=None, work=None, stream=None, check=True, timeout_s=0.0):
-    """In-place QR of the column-major float64 CUDA tensor ``A`` (M x N,
-    strides (1, lda)).  Returns the workspace (it holds the T factors)."""
+    """In-place QR of the column-major float64 (or float32: FP32 tile
+    kernels) CUDA tensor ``A`` (M x N, strides (1, lda)).  Returns the
+    workspace (it holds the T factors)."""
     import torch
 
-    if A.dtype != torch.float64 or not A.is_cuda or A.dim() != 2:
-        raise ValueError("A must be a 2-D float64 CUDA tensor")
+    if A.dtype not in (torch.float64, torch.float32) or not A.is_cuda or A.dim() != 2:
+        raise ValueError("A must be a 2-D float64 or float32 CUDA tensor")
+    f32 = A.dtype == torch.float32
     M, N = A.shape
     if A.stride(0) != 1:
         raise ValueError("A must be column-major (stride(0) == 1); use colmajor()")
     lda = A.stride(1) if N > 1 else max(M, 1)
     if work is None:
-        work = Workspace(M, N, params, device=A.device)
+        work = Workspace(M, N, params, device=A.device, f32=f32)
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
-    _lib.factor_ptr(A.data_ptr(), M, N, lda, params, exec_, work.ptr, work.bytes, s.cuda_stream)
+    fn = _lib.factor_f32_ptr if f32 else _lib.factor_ptr
+    fn(A.data_ptr(), M, N, lda, params, exec_, work.ptr, work.bytes, s.cuda_stream)
     if check:
         st, info = _lib.status(work.ptr, s.cuda_stream, timeout_s=timeout_s, detail=True)
         if st != 0:

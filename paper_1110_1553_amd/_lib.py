@@ -42,7 +42,7 @@ TASK_DTYPE = np.dtype([("op", "u1"), ("chunk", "u1"), ("row", "<u2"), ("killer",
                        ("j", "<u2"), ("pad", "<u2"), ("v", "<u4", (3,))])
 
 EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size", "hqr_factor",
-           "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size", "hqr_lstsq",
+           "hqr_workspace_size_f32", "hqr_factor_f32", "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size", "hqr_lstsq",
            "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_timeline", "hqr_version",
            "hqr_batch_create", "hqr_batch_workspace_size", "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run",
            "hqr_batch_status", "hqr_batch_destroy", "hqr_lstsq_batched", "hqr_lstsq_batched_workspace_size")
@@ -72,6 +72,8 @@ def load():
     lib.hqr_plan_tasks.argtypes = [i32, i32, P(Params), i32, vp, i64, P(i64)]
     lib.hqr_workspace_size.argtypes = [i64, i64, P(Params), P(ctypes.c_size_t)]
     lib.hqr_factor.argtypes = [vp, i64, i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
+    lib.hqr_workspace_size_f32.argtypes = [i64, i64, P(Params), P(ctypes.c_size_t)]
+    lib.hqr_factor_f32.argtypes = [vp, i64, i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
     lib.hqr_apply_workspace_size.argtypes = [i64, i32, P(Params), P(ctypes.c_size_t)]
     apply_args = [i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp, i64, i32, vp, ctypes.c_size_t, vp]
     lib.hqr_apply_qt.argtypes = apply_args
@@ -102,7 +104,7 @@ def load():
     lib.hqr_version.restype = ctypes.c_char_p
     for name in ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size",
                  "hqr_factor", "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size",
-                 "hqr_lstsq", "hqr_status", "hqr_status_ex", "hqr_batch_create", "hqr_batch_workspace_size",
+                 "hqr_lstsq", "hqr_status", "hqr_status_ex", "hqr_workspace_size_f32", "hqr_factor_f32", "hqr_batch_create", "hqr_batch_workspace_size",
                  "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run", "hqr_batch_status", "hqr_lstsq_batched",
                  "hqr_lstsq_batched_workspace_size"):
         getattr(lib, name).restype = ctypes.c_int
@@ -179,6 +181,20 @@ def factor_ptr(dA: int, M: int, N: int, lda: int, params: Params, exec_: Exec, d
                            ctypes.byref(exec_) if exec_ is not None else None,
                            ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(stream))
     _check("hqr_factor", rc)
+
+
+def workspace_size_f32(M: int, N: int, params: Params) -> int:
+    n = ctypes.c_size_t()
+    _check("hqr_workspace_size_f32", load().hqr_workspace_size_f32(M, N, ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def factor_f32_ptr(dA: int, M: int, N: int, lda: int, params: Params, exec_: Exec, dwork: int, work_bytes: int,
+                   stream: int) -> None:
+    rc = load().hqr_factor_f32(ctypes.c_void_p(dA), M, N, lda, ctypes.byref(params),
+                               ctypes.byref(exec_) if exec_ is not None else None,
+                               ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(stream))
+    _check("hqr_factor_f32", rc)
 
 
 def apply_workspace_size(M: int, nrhs: int, params: Params) -> int:

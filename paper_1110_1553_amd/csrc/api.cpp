@@ -190,9 +190,13 @@ int check_apply_args(int64_t M, int64_t N, const hqr_params* params, const void*
 // are transformed by Q^T as further tile columns) into the workspace's
 // tiles, run every task of the plan, copy A back when copy_a_out.  The
 // caller has checked the arguments.
-int run_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& p, const hqr_exec& ex, void* dwork,
-               double* dB, int64_t ldb, int32_t nrhs, void* stream, bool copy_a_out) {
-  const Layout L = layout_for(M, N, p, nrhs);
+// f32: the factorization runs in FP32 on float tiles; a_f32: dA holds
+// float (else double, rounded to float on the way in when f32).
+int run_factor(void* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& p, const hqr_exec& ex, void* dwork,
+               double* dB, int64_t ldb, int32_t nrhs, void* stream, bool copy_a_out, bool f32 = false,
+               bool a_f32 = false) {
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  const Layout L = layout_for(M, N, p, nrhs, es);
   ColumnChunks cc;
   cc.last_a = L.last_a;
   cc.nrhs_cols = nrhs;
@@ -218,14 +222,17 @@ int run_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& 
   a.B = nullptr;
   a.A = (double*)(w + L.tiles);
   a.lda = p.nb;
-  if ((rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, p.nb, L.mt, L.nt, true, stream))) return rc;
-  double* Bt = a.A + (size_t)L.mt * L.nt * p.nb * p.nb;
-  if (nrhs > 0 && (rc = launch_tile_copy(dB, ldb, Bt, M, nrhs, p.nb, p.nb, L.mt, L.nrt, true, stream))) return rc;
+  if ((rc = launch_tile_copy(dA, a_f32, lda, a.A, f32, M, N, p.nb, p.nb, L.mt, L.nt, true, stream))) return rc;
+  void* Bt = (char*)a.A + (size_t)L.mt * L.nt * p.nb * p.nb * es;
+  if (nrhs > 0 && (rc = launch_tile_copy(dB, 0, ldb, Bt, f32, M, nrhs, p.nb, p.nb, L.mt, L.nrt, true, stream)))
+    return rc;
   const int64_t nwords = (int64_t)((L.tg - L.ctrl) / sizeof(int32_t));  // ctrl + counters
   if ((rc = launch_zero_i32(a.ctrl, nwords, stream))) return rc;
-  int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb);
-  if ((rc = launch_persistent(p.nb, a, workers, stream))) return rc;
-  if (copy_a_out && (rc = launch_tile_copy(dA, lda, a.A, M, N, p.nb, p.nb, L.mt, L.nt, false, stream))) return rc;
+  int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb, f32);
+  if ((rc = launch_persistent(p.nb, a, workers, stream, f32))) return rc;
+  if (copy_a_out &&
+      (rc = launch_tile_copy(dA, a_f32, lda, a.A, f32, M, N, p.nb, p.nb, L.mt, L.nt, false, stream)))
+    return rc;
   return 0;
 }
 
@@ -320,6 +327,32 @@ int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* 
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -6;
   return run_factor(dA, M, N, lda, *params, ex, dwork, nullptr, 0, 0, stream, true);
+}
+
+int hqr_workspace_size_f32(int64_t M, int64_t N, const hqr_params* params, size_t* bytes) {
+  if (M < 1) return -1;
+  if (N < 1 || N > M) return -2;
+  if (!params || check_params(*params)) return -3;
+  if (!bytes) return -4;
+  *bytes = layout_for(M, N, *params, 0, sizeof(float)).total;
+  return 0;
+}
+
+int hqr_factor_f32(float* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params, const hqr_exec* exec,
+                   void* dwork, size_t work_bytes, void* stream) {
+  if (!dA) return -1;
+  if (M < 1 || M < N) return -2;
+  if (N < 1) return -3;
+  if (lda < M) return -4;
+  if (!params || check_params(*params)) return -5;
+  if (!dwork) return -7;
+  const Layout L = layout_for(M, N, *params, 0, sizeof(float));
+  if (L.mt > 65535 || L.nt > 65535) return -2;
+  if (work_bytes < L.total) return -8;
+  hqr_exec ex{0, 0, 0};
+  if (exec) ex = *exec;
+  if (ex.order != 0 && ex.order != 1) return -6;
+  return run_factor(dA, M, N, lda, *params, ex, dwork, nullptr, 0, 0, stream, true, true, true);
 }
 
 int hqr_apply_workspace_size(int64_t M, int32_t nrhs, const hqr_params* params, size_t* bytes) {

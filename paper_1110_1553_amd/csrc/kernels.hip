@@ -35,6 +35,16 @@ namespace hqr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+// Element type E of a factorization: double (FP64 MFMA) or float (FP32
+// MFMA).  V4<E> is one MFMA accumulator block per lane, V2<E> a pair.
+template <typename E> struct VecOf;
+template <> struct VecOf<double> { typedef d4 v4; typedef d2 v2; };
+template <> struct VecOf<float> { typedef f4 v4; typedef f2 v2; };
+template <typename E> using V4 = typename VecOf<E>::v4;
+template <typename E> using V2 = typename VecOf<E>::v2;
 
 constexpr int IB = 16;      // inner blocking (columns per panel)
 constexpr int LDV = IB + 1; // LDS row stride of a staged panel (odd: no bank conflicts)
@@ -45,6 +55,12 @@ enum Kind { K_UNM = 0, K_TS = 1, K_TT = 2 };
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double esqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float esqrt(float x) { return sqrtf(x); }
 
 // Global-memory accessors for tile data inside the persistent launch.
 //
@@ -61,12 +77,19 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 #define HQR_GLOBAL_AS __attribute__((address_space(1)))
 #endif
 typedef HQR_GLOBAL_AS double gdouble;
+typedef HQR_GLOBAL_AS float gfloat;
 
 __device__ __forceinline__ double gload(const double* p) {
   return __hip_atomic_load((gdouble*)const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void gstore(double* p, double v) {
   __hip_atomic_store((gdouble*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float gload(const float* p) {
+  return __hip_atomic_load((gfloat*)const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gstore(float* p, float v) {
+  __hip_atomic_store((gfloat*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ d2 gload2(const double* p) {
   d2 r;
@@ -87,27 +110,45 @@ __device__ __forceinline__ void stores_done() { __builtin_amdgcn_s_waitcnt(0); }
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 constexpr int kCoherent = 16;  // cache policy bit: coherent at device scope
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const double* base) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
   // the base is wave-uniform by construction; say so, so that it lives in
   // scalar registers
   const uint64_t u = (uint64_t)base;
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
-  double* b = (double*)(((uint64_t)hi << 32) | lo);
+  void* b = (void*)(((uint64_t)hi << 32) | lo);
   return __builtin_amdgcn_make_buffer_rsrc(b, 0, 0x7fffffff, 0x00020000);
 }
-__device__ __forceinline__ d2 bload2(__amdgpu_buffer_rsrc_t r, int off) {
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+// Two consecutive elements at element offset `off` (16 bytes of double, 8
+// of float) and four consecutive elements (two or one 16-byte accesses).
+template <typename E>
+__device__ __forceinline__ V2<E> bload2(__amdgpu_buffer_rsrc_t r, int off);
+template <>
+__device__ __forceinline__ d2 bload2<double>(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off * 8, 0, kCoherent));
+}
+template <>
+__device__ __forceinline__ f2 bload2<float>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(r, off * 4, 0, kCoherent));
 }
 __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, int off, d2 v) {
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off * 8, 0, kCoherent);
 }
-__device__ __forceinline__ d4 ld4(__amdgpu_buffer_rsrc_t r, int off) {
-  const d2 x = bload2(r, off);
-  const d2 y = bload2(r, off + 2);
+template <typename E>
+__device__ __forceinline__ V4<E> ld4(__amdgpu_buffer_rsrc_t r, int off);
+template <>
+__device__ __forceinline__ d4 ld4<double>(__amdgpu_buffer_rsrc_t r, int off) {
+  const d2 x = bload2<double>(r, off);
+  const d2 y = bload2<double>(r, off + 2);
   d4 v;
   v.x = x.x; v.y = x.y; v.z = y.x; v.w = y.y;
   return v;
+}
+template <>
+__device__ __forceinline__ f4 ld4<float>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off * 4, 0, kCoherent));
 }
 __device__ __forceinline__ void st4(__amdgpu_buffer_rsrc_t r, int off, d4 v) {
   d2 x, y;
@@ -115,9 +156,16 @@ __device__ __forceinline__ void st4(__amdgpu_buffer_rsrc_t r, int off, d4 v) {
   bstore2(r, off, x);
   bstore2(r, off + 2, y);
 }
+__device__ __forceinline__ void st4(__amdgpu_buffer_rsrc_t r, int off, f4 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off * 4, 0, kCoherent);
+}
 
 // One DPP step on a double: each lane receives the value of the lane picked
 // by `ctrl` inside its row of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
@@ -129,7 +177,8 @@ __device__ __forceinline__ double dpp(double v) {
 // Sum over the 16 lanes of a DPP row, returned in every lane of the row.
 // Each step adds two partial sums in an order that does not depend on the
 // lane (addition is commutative), so all 16 lanes hold bitwise the same sum.
-__device__ __forceinline__ double sum16(double v) {
+template <typename E>
+__device__ __forceinline__ E sum16(E v) {
   v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp<0x124>(v);  // row_ror:4
@@ -146,12 +195,12 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int NB>
+template <typename E, int NB>
 struct Smem {
-  double V[2][NB * LDV];  // staged V panels (row-major, stride LDV)
-  double T[2][IB * LDV];  // staged T blocks
-  double R[IB * LDV];     // diagonal block of the killer's R (TS/TT panel kernels)
-  double tau[IB];
+  E V[2][NB * LDV];  // staged V panels (row-major, stride LDV)
+  E T[2][IB * LDV];  // staged T blocks
+  E R[IB * LDV];     // diagonal block of the killer's R (TS/TT panel kernels)
+  E tau[IB];
   int task;  // index of the task taken by the workgroup (-1: launch aborted)
   int ok;    // 1 if the task's dependencies were met, 0 if the launch was aborted
 };
@@ -160,9 +209,9 @@ struct Smem {
 // the launch's dynamic LDS.
 extern __shared__ __attribute__((aligned(16))) double hqr_lds[];
 
-template <int NB>
-__device__ __forceinline__ Smem<NB>& smem() {
-  return *reinterpret_cast<Smem<NB>*>(hqr_lds);
+template <typename E, int NB>
+__device__ __forceinline__ Smem<E, NB>& smem() {
+  return *reinterpret_cast<Smem<E, NB>*>(hqr_lds);
 }
 
 // Lane coordinates.
@@ -177,6 +226,14 @@ struct Lane {
   }
 };
 
+// MFMA row whose reduction index this lane supplies in the products with
+// V^T and T^T: pi(q) for FP64 (its accumulator rows are interleaved),
+// q itself for FP32 (element r of lane l is MFMA row 4 (l / 16) + r).
+template <typename E>
+__device__ __forceinline__ int mrow(const Lane& L) {
+  return sizeof(E) == 8 ? L.pq : L.q;
+}
+
 // ---------------------------------------------------------------------------
 // Block-reflector application of one panel to one 16-column strip held by a
 // wave.  `acc` holds rows 0..NB-1 of the strip of the matrix the reflectors
@@ -189,7 +246,7 @@ struct Lane {
 //
 // Active rows: UNM rows >= 16p (V unit lower triangular), TS all rows
 // (V dense), TT rows < 16p + 16 (V upper triangular).
-template <int NB, int KIND>
+template <typename E, int NB, int KIND>
 __device__ __forceinline__ bool row_block_active(int rb, int p) {
   return (KIND == K_UNM) ? (rb >= p) : (KIND == K_TT ? rb <= p : true);
 }
@@ -202,28 +259,28 @@ __device__ __forceinline__ bool row_block_active(int rb, int p) {
 //
 // A wave may hold SPW strips (columns 16 w + 64 s, s < SPW, of the chunk):
 // every V operand read from LDS then feeds SPW products.
-template <int NB, int KIND, bool TRANS, int SPW>
-__device__ __forceinline__ void apply_panel_n(d4 (&acc)[SPW][NB / 16], const double* __restrict__ Vs,
-                                              const double* __restrict__ Ts, int p, double* c1, int64_t ldc,
+template <typename E, int NB, int KIND, bool TRANS, int SPW>
+__device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const E* __restrict__ Vs,
+                                              const E* __restrict__ Ts, int p, E* c1, int64_t ldc,
                                               const Lane& L) {
   constexpr int NRB = NB / 16;
-  d4 c1v[SPW];
-  d4 w0[SPW], w1[SPW];
+  V4<E> c1v[SPW];
+  V4<E> w0[SPW], w1[SPW];
   const __amdgpu_buffer_rsrc_t rc1 = rsrc(c1);
 #pragma unroll
   for (int s = 0; s < SPW; ++s) {
-    c1v[s] = d4{0.0, 0.0, 0.0, 0.0};
-    if (KIND != K_UNM) c1v[s] = ld4(rc1, 4 * L.g + (L.q + 64 * s) * (int)ldc);
-    w0[s] = d4{0.0, 0.0, 0.0, 0.0};
+    c1v[s] = V4<E>{E(0), E(0), E(0), E(0)};
+    if (KIND != K_UNM) c1v[s] = ld4<E>(rc1, 4 * L.g + (L.q + 64 * s) * (int)ldc);
+    w0[s] = V4<E>{E(0), E(0), E(0), E(0)};
     w1[s] = w0[s];
   }
   // ---- W = V^T acc: group rb = 4 products per strip, alternating two partial sums
   {
-    const double* va = Vs + 4 * L.g * LDV + L.pq;  // + (16 rb + r) * LDV
-    double a[4], an[4];
+    const E* va = Vs + 4 * L.g * LDV + mrow<E>(L);  // + (16 rb + r) * LDV
+    E a[4], an[4];
     const int lo = (KIND == K_UNM) ? p : 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a[r] = 0.0;
+    for (int r = 0; r < 4; ++r) a[r] = E(0);
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
       if (rb == lo) {
@@ -232,9 +289,9 @@ __device__ __forceinline__ void apply_panel_n(d4 (&acc)[SPW][NB / 16], const dou
       }
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) {
-      if (row_block_active<NB, KIND>(rb, p)) {
+      if (row_block_active<E, NB, KIND>(rb, p)) {
         __builtin_amdgcn_sched_barrier(0);
-        if (rb + 1 < NRB && row_block_active<NB, KIND>(rb + 1, p)) {
+        if (rb + 1 < NRB && row_block_active<E, NB, KIND>(rb + 1, p)) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) an[r] = va[(16 * (rb + 1) + r) * LDV];
         }
@@ -254,16 +311,16 @@ __device__ __forceinline__ void apply_panel_n(d4 (&acc)[SPW][NB / 16], const dou
       }
     }
   }
-  d4 wn[SPW];
+  V4<E> wn[SPW];
   {
-    double t[4];
+    E t[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) t[r] = TRANS ? Ts[(4 * L.g + r) * LDV + L.pq] : Ts[L.pq * LDV + 4 * L.g + r];
+    for (int r = 0; r < 4; ++r) t[r] = TRANS ? Ts[(4 * L.g + r) * LDV + mrow<E>(L)] : Ts[mrow<E>(L) * LDV + 4 * L.g + r];
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
-      d4 w = w0[s] + w1[s];
+      V4<E> w = w0[s] + w1[s];
       if (KIND != K_UNM) w += c1v[s];
-      d4 w2t = {0.0, 0.0, 0.0, 0.0};
+      V4<E> w2t = {E(0), E(0), E(0), E(0)};
 #pragma unroll
       for (int r = 0; r < 4; ++r) w2t = mfma(t[r], w[r], w2t);
       if (KIND != K_UNM) st4(rc1, 4 * L.g + (L.q + 64 * s) * (int)ldc, c1v[s] - w2t);
@@ -272,18 +329,18 @@ __device__ __forceinline__ void apply_panel_n(d4 (&acc)[SPW][NB / 16], const dou
   }
   // ---- acc -= V W: groups of two row blocks, products interleaved
   {
-    const double* vc = Vs + L.pq * LDV + 4 * L.g;  // + 16 rb LDV + r
+    const E* vc = Vs + mrow<E>(L) * LDV + 4 * L.g;  // + 16 rb LDV + r
 #pragma unroll
     for (int rb = 0; rb < NRB; rb += 2) {
-      const bool act0 = row_block_active<NB, KIND>(rb, p);
-      const bool act1 = row_block_active<NB, KIND>(rb + 1, p);
+      const bool act0 = row_block_active<E, NB, KIND>(rb, p);
+      const bool act1 = row_block_active<E, NB, KIND>(rb + 1, p);
       if (act0 || act1) {
         __builtin_amdgcn_sched_barrier(0);
-        double b0[4], b1[4];
+        E b0[4], b1[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          b0[r] = act0 ? vc[16 * rb * LDV + r] : 0.0;
-          b1[r] = act1 ? vc[16 * (rb + 1) * LDV + r] : 0.0;
+          b0[r] = act0 ? vc[16 * rb * LDV + r] : E(0);
+          b1[r] = act1 ? vc[16 * (rb + 1) * LDV + r] : E(0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -300,25 +357,25 @@ __device__ __forceinline__ void apply_panel_n(d4 (&acc)[SPW][NB / 16], const dou
 }
 
 // One strip per wave.
-template <int NB, int KIND, bool TRANS = true>
-__device__ __forceinline__ void apply_panel(d4 (&acc)[NB / 16], const double* __restrict__ Vs,
-                                            const double* __restrict__ Ts, int p, double* c1, int64_t ldc,
+template <typename E, int NB, int KIND, bool TRANS = true>
+__device__ __forceinline__ void apply_panel(V4<E> (&acc)[NB / 16], const E* __restrict__ Vs,
+                                            const E* __restrict__ Ts, int p, E* c1, int64_t ldc,
                                             const Lane& L) {
-  apply_panel_n<NB, KIND, TRANS, 1>(reinterpret_cast<d4 (&)[1][NB / 16]>(acc), Vs, Ts, p, c1, ldc, L);
+  apply_panel_n<E, NB, KIND, TRANS, 1>(reinterpret_cast<V4<E> (&)[1][NB / 16]>(acc), Vs, Ts, p, c1, ldc, L);
 }
 
-template <int NB, int KIND>
-__device__ __forceinline__ void load_strip(d4 (&acc)[NB / 16], const double* base, int64_t ld, int p,
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void load_strip(V4<E> (&acc)[NB / 16], const E* base, int64_t ld, int p,
                                            const Lane& L) {
 #pragma unroll
   for (int rb = 0; rb < NB / 16; ++rb) {
     const bool active = (KIND == K_UNM) ? (rb >= p) : (KIND == K_TT ? rb <= p : true);
-    if (active) acc[rb] = ld4(rsrc(base), 16 * rb + 4 * L.g + L.q * (int)ld);
+    if (active) acc[rb] = ld4<E>(rsrc(base), 16 * rb + 4 * L.g + L.q * (int)ld);
   }
 }
 
-template <int NB, int KIND>
-__device__ __forceinline__ void store_strip(const d4 (&acc)[NB / 16], double* base, int64_t ld, int p,
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void store_strip(const V4<E> (&acc)[NB / 16], E* base, int64_t ld, int p,
                                             const Lane& L) {
 #pragma unroll
   for (int rb = 0; rb < NB / 16; ++rb) {
@@ -331,32 +388,32 @@ __device__ __forceinline__ void store_strip(const d4 (&acc)[NB / 16], double* ba
 // LDS with the structure of the kind: UNM unit diagonal and zeros above it
 // in the diagonal block; TT zeros below the diagonal; rows that no product
 // reads are skipped.
-template <int NB>
+template <typename E, int NB>
 struct PanelPrefetch {
   static constexpr int PER = NB * 8 / NT;  // double2 loads per thread
-  d2 v[PER];
-  double t;
+  V2<E> v[PER];
+  E t;
 };
 
-template <int NB, int KIND>
-__device__ __forceinline__ void prefetch_panel(PanelPrefetch<NB>& pf, const double* V, int64_t ld,
-                                               const double* Tblk, int p) {
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void prefetch_panel(PanelPrefetch<E, NB>& pf, const E* V, int64_t ld,
+                                               const E* Tblk, int p) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int it = 0; it < PanelPrefetch<NB>::PER; ++it) {
+  for (int it = 0; it < PanelPrefetch<E, NB>::PER; ++it) {
     const int e = it * NT + tid;
     const int col = e / (NB / 2), row = 2 * (e % (NB / 2));
     const bool needed = (KIND == K_UNM) ? (row >= 16 * p) : (KIND == K_TT ? row < 16 * p + 16 : true);
-    if (needed) pf.v[it] = bload2(rsrc(V), row + (16 * p + col) * (int)ld);
+    if (needed) pf.v[it] = bload2<E>(rsrc(V), row + (16 * p + col) * (int)ld);
   }
   if (tid < 256) pf.t = gload(Tblk + tid);
 }
 
-template <int NB, int KIND>
-__device__ __forceinline__ void stage_panel(const PanelPrefetch<NB>& pf, double* Vs, double* Ts, int p) {
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void stage_panel(const PanelPrefetch<E, NB>& pf, E* Vs, E* Ts, int p) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int it = 0; it < PanelPrefetch<NB>::PER; ++it) {
+  for (int it = 0; it < PanelPrefetch<E, NB>::PER; ++it) {
     const int e = it * NT + tid;
     const int col = e / (NB / 2), row = 2 * (e % (NB / 2));
     const bool needed = (KIND == K_UNM) ? (row >= 16 * p) : (KIND == K_TT ? row < 16 * p + 16 : true);
@@ -364,11 +421,11 @@ __device__ __forceinline__ void stage_panel(const PanelPrefetch<NB>& pf, double*
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int r = row + h;
-        double x = pf.v[it][h];
+        E x = pf.v[it][h];
         const int a = r - 16 * p;  // row inside the diagonal block
         if (a >= 0 && a < 16) {
-          if (KIND == K_UNM) x = (a == col) ? 1.0 : (a < col ? 0.0 : x);
-          if (KIND == K_TT) x = (a > col) ? 0.0 : x;
+          if (KIND == K_UNM) x = (a == col) ? E(1) : (a < col ? E(0) : x);
+          if (KIND == K_TT) x = (a > col) ? E(0) : x;
         }
         Vs[r * LDV + col] = x;
       }
@@ -384,32 +441,32 @@ __device__ __forceinline__ void stage_panel(const PanelPrefetch<NB>& pf, double*
 //   C1: killer tile (TS/TT).
 // TRANS applies Q^T (the panels in factorization order, T^T); otherwise Q
 // (the panels in reverse order, T).
-template <int NB, int KIND, bool TRANS, int CW>
-__device__ __forceinline__ void run_update(Smem<NB>& sm, const double* V, const double* T, double* C1, double* C2,
+template <typename E, int NB, int KIND, bool TRANS, int CW>
+__device__ __forceinline__ void run_update(Smem<E, NB>& sm, const E* V, const E* T, E* C1, E* C2,
                                            int64_t ld) {
   constexpr int NP = NB / IB;
   const Lane L;
   const bool on = 16 * L.wave < CW;  // waves holding a strip of the chunk (uniform per wave)
-  d4 acc[NB / 16];
+  V4<E> acc[NB / 16];
   const int64_t coloff = (int64_t)(16 * L.wave) * ld;
-  if (on) load_strip<NB, K_TS>(acc, C2 + coloff, ld, 0, L);
-  PanelPrefetch<NB> pf;
+  if (on) load_strip<E, NB, K_TS>(acc, C2 + coloff, ld, 0, L);
+  PanelPrefetch<E, NB> pf;
   const int pfirst = TRANS ? 0 : NP - 1;
-  prefetch_panel<NB, KIND>(pf, V, ld, T + pfirst * 256, pfirst);
+  prefetch_panel<E, NB, KIND>(pf, V, ld, T + pfirst * 256, pfirst);
 #pragma unroll 1
   for (int it = 0; it < NP; ++it) {
     const int p = TRANS ? it : NP - 1 - it;
-    double* Vs = sm.V[it & 1];
-    double* Ts = sm.T[it & 1];
-    stage_panel<NB, KIND>(pf, Vs, Ts, p);
+    E* Vs = sm.V[it & 1];
+    E* Ts = sm.T[it & 1];
+    stage_panel<E, NB, KIND>(pf, Vs, Ts, p);
     lds_barrier();
     if (it + 1 < NP) {
       const int pn = TRANS ? p + 1 : p - 1;
-      prefetch_panel<NB, KIND>(pf, V, ld, T + pn * 256, pn);
+      prefetch_panel<E, NB, KIND>(pf, V, ld, T + pn * 256, pn);
     }
-    if (on) apply_panel<NB, KIND, TRANS>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p, ld, L);
+    if (on) apply_panel<E, NB, KIND, TRANS>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p, ld, L);
   }
-  if (on) store_strip<NB, K_TS>(acc, C2 + coloff, ld, 0, L);
+  if (on) store_strip<E, NB, K_TS>(acc, C2 + coloff, ld, 0, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -433,6 +490,9 @@ __device__ __forceinline__ void run_update(Smem<NB>& sm, const double* V, const 
 // columns are read and written once per block instead of once per panel.
 
 // Reads lane `lane` (wave-uniform) of a double held in VGPRs.
+__device__ __forceinline__ float readlane(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
 __device__ __forceinline__ double readlane(double v, int lane) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
@@ -448,11 +508,11 @@ __device__ __forceinline__ double readlane(double v, int lane) {
 // published through LDS (double buffered), which costs one workgroup
 // barrier per column.  Leaves V_p in sm.V[0] (with the structure of the
 // kind), T_p in sm.T[0] and in `T`, and the factored columns in A (and R).
-template <int NB, int KIND>
-__device__ __forceinline__ void panel_columns(double* A, double* R, double* T, int p) {
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
   constexpr int NM = NB / 16;  // row slots per thread
   p = __builtin_amdgcn_readfirstlane(p);  // uniform: row-slot guards become scalar branches
-  Smem<NB>& sm = smem<NB>();
+  Smem<E, NB>& sm = smem<E, NB>();
   const int tid = threadIdx.x;
   // waves 0-3 hold the panel; waves 4-7 only take part in the barriers
   const bool ct = tid < 256;
@@ -464,72 +524,72 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
   // TT rows <= c0 + 15.  The other slots hold zeros; the column loop runs
   // over all slots (branch-free), only loads and stores skip them.
   const int nm = (KIND == K_UNM) ? NM - p : (KIND == K_TT ? p + 1 : NM);
-  double* Vs = sm.V[0];
-  double* Ts = sm.T[0];
-  double* Zs = sm.R;     // Gram entries v_i^T v_j of the panel
-  double* Vb = sm.V[1];  // published reflector, two buffers of NB
-  double* col = A + (int64_t)(c0 + cc) * NB;
-  double x[NM];
+  E* Vs = sm.V[0];
+  E* Ts = sm.T[0];
+  E* Zs = sm.R;     // Gram entries v_i^T v_j of the panel
+  E* Vb = sm.V[1];  // published reflector, two buffers of NB
+  E* col = A + (int64_t)(c0 + cc) * NB;
+  E x[NM];
 #pragma unroll
   for (int m = 0; m < NM; ++m) {
     const int r = base + q + 16 * m;
     // TT: rows below the diagonal hold the tile's own GEQRT reflectors
     const bool act = ct && m < nm && (KIND != K_TT || r <= c0 + cc);
-    x[m] = act ? gload(col + r) : 0.0;
+    x[m] = act ? gload(col + r) : E(0);
   }
-  double rv = 0.0;  // TS/TT: R(c0 + q, c0 + cc) of the killer's diagonal block
+  E rv = E(0);  // TS/TT: R(c0 + q, c0 + cc) of the killer's diagonal block
   if (KIND != K_UNM && ct && q <= cc) rv = gload(R + (c0 + q) + (int64_t)(c0 + cc) * NB);
-  if (ct) Zs[cc * LDV + q] = 0.0;  // entries (i, j) with i >= j stay zero
+  if (ct) Zs[cc * LDV + q] = E(0);  // entries (i, j) with i >= j stay zero
   // T is formed column by column on lanes 0-15 of wave 4 (idle in the column
   // loop), one row of T per lane: column k = jj - 1 once z(0:k, k) and
   // tau_k are visible (after the barrier of iteration jj).
   //   T(k,k) = tau_k,  T(i,k) = -tau_k sum_{i <= l < k} T(i,l) z(l,k)
   const bool tl = tid >= 256 && tid < 272;
   const int ti = tid - 256;
-  double trow[16];
+  E trow[16];
 #pragma unroll
-  for (int l = 0; l < 16; ++l) trow[l] = 0.0;
+  for (int l = 0; l < 16; ++l) trow[l] = E(0);
   auto t_column = [&](int k) {
-    const double tk = sm.tau[k];
-    double acc = 0.0;
+    const E tk = sm.tau[k];
+    E acc = E(0);
 #pragma unroll
     for (int l = 0; l < 16; ++l)
       if (l < k) acc += trow[l] * Zs[l * LDV + k];  // trow[l] = 0 for l < ti
-    const double val = (ti < k) ? -tk * acc : (ti == k ? tk : 0.0);
+    const E val = (ti < k) ? -tk * acc : (ti == k ? tk : E(0));
 #pragma unroll
     for (int l = 0; l < 16; ++l)
       if (l == k) trow[l] = val;
   };
   for (int jj = 0; jj < 16; ++jj) {
-    double* vb = Vb + (jj & 1) * NB;
+    E* vb = Vb + (jj & 1) * NB;
     if (cc == jj) {
       // the group owning column jj: wave jj / 4, lanes 16 (jj % 4) .. + 15;
       // the head is in its lane q = jj (GEQRT: slot 0; TS/TT: rv)
-      const double alpha = readlane(KIND == K_UNM ? x[0] : rv, (jj & 3) * 16 + jj);
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      const E alpha = readlane(KIND == K_UNM ? x[0] : rv, (jj & 3) * 16 + jj);
+      E s0 = E(0), s1 = E(0), s2 = E(0), s3 = E(0);
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        double t = x[m];
-        if (KIND == K_UNM && m == 0 && q <= jj) t = 0.0;  // rows <= j are not in the tail
+        E t = x[m];
+        if (KIND == K_UNM && m == 0 && q <= jj) t = E(0);  // rows <= j are not in the tail
         if ((m & 3) == 0) s0 += t * t;
         if ((m & 3) == 1) s1 += t * t;
         if ((m & 3) == 2) s2 += t * t;
         if ((m & 3) == 3) s3 += t * t;
       }
-      const double ss = sum16((s0 + s1) + (s2 + s3));
-      double tau = 0.0, beta = alpha, scale = 1.0;
-      if (ss != 0.0) {
-        beta = sqrt(alpha * alpha + ss);
-        if (alpha >= 0.0) beta = -beta;
+      const E ss = sum16((s0 + s1) + (s2 + s3));
+      E tau = E(0), beta = alpha, scale = E(1);
+      if (ss != E(0)) {
+        beta = esqrt(alpha * alpha + ss);
+        if (alpha >= E(0)) beta = -beta;
         tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
+        scale = E(1) / (alpha - beta);
       }
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
         if (KIND == K_UNM && m == 0) {
           if (q > jj) x[0] *= scale;
           if (q == jj) x[0] = beta;
-          vb[q] = (q > jj) ? x[0] : (q == jj ? 1.0 : 0.0);
+          vb[q] = (q > jj) ? x[0] : (q == jj ? E(1) : E(0));
         } else {
           x[m] *= scale;
           vb[q + 16 * m] = x[m];
@@ -541,9 +601,9 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
     lds_barrier();
     if (tl && jj > 0) t_column(jj - 1);
     if (ct && cc != jj) {
-      const double tau = sm.tau[jj];
-      double v[NM];
-      double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+      const E tau = sm.tau[jj];
+      E v[NM];
+      E d0 = E(0), d1 = E(0), d2 = E(0), d3 = E(0);
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
         v[m] = vb[q + 16 * m];
@@ -555,10 +615,10 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
       // TS/TT: the unit entry of v sits in row j of the triangle on top,
       // where lane q = jj of column c0 + cc holds R(j, c0 + cc)
       if (KIND != K_UNM && cc > jj && q == jj) d0 += rv;
-      const double d = sum16((d0 + d1) + (d2 + d3));
+      const E d = sum16((d0 + d1) + (d2 + d3));
       if (cc > jj) {
-        if (tau != 0.0) {
-          const double f = tau * d;
+        if (tau != E(0)) {
+          const E f = tau * d;
 #pragma unroll
           for (int m = 0; m < NM; ++m) x[m] -= f * v[m];
           if (KIND != K_UNM && q == jj) rv -= f;
@@ -586,11 +646,11 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
       const bool act = KIND != K_TT || r <= c0 + cc;
       if (act) {
         gstore(col + r, x[m]);
-        double vv = x[m];
-        if (KIND == K_UNM && m == 0 && q <= cc) vv = (q == cc) ? 1.0 : 0.0;  // unit diagonal, R above
+        E vv = x[m];
+        if (KIND == K_UNM && m == 0 && q <= cc) vv = (q == cc) ? E(1) : E(0);  // unit diagonal, R above
         Vs[r * LDV + cc] = vv;
       } else {
-        Vs[r * LDV + cc] = 0.0;  // TT: zero below the diagonal of V
+        Vs[r * LDV + cc] = E(0);  // TT: zero below the diagonal of V
       }
     }
   }
@@ -602,20 +662,20 @@ __device__ __forceinline__ void panel_columns(double* A, double* R, double* T, i
 
 // Applies panel p (V_p, T_p staged in sm.V[0], sm.T[0]) to the strips
 // p+1 .. s_last of the tile(s) (at most 3): wave w takes strip p + 1 + w.
-template <int NB, int KIND>
-__device__ __forceinline__ void panel_strips(double* A, double* R, int p, int s_last) {
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void panel_strips(E* A, E* R, int p, int s_last) {
   p = __builtin_amdgcn_readfirstlane(p);
   s_last = __builtin_amdgcn_readfirstlane(s_last);
-  Smem<NB>& sm = smem<NB>();
+  Smem<E, NB>& sm = smem<E, NB>();
   const Lane L;
   const int s = p + 1 + L.wave;
   if (s <= s_last) {
-    d4 acc[NB / 16];
-    double* strip = A + (int64_t)(16 * s) * NB;
-    load_strip<NB, KIND>(acc, strip, NB, p, L);
-    apply_panel<NB, KIND>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p,
+    V4<E> acc[NB / 16];
+    E* strip = A + (int64_t)(16 * s) * NB;
+    load_strip<E, NB, KIND>(acc, strip, NB, p, L);
+    apply_panel<E, NB, KIND>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p,
                           NB, L);
-    store_strip<NB, KIND>(acc, strip, NB, p, L);
+    store_strip<E, NB, KIND>(acc, strip, NB, p, L);
   }
   stores_done();
   __syncthreads();  // the next panel's column loop reads these strips from memory
@@ -626,11 +686,11 @@ __device__ __forceinline__ void panel_strips(double* A, double* R, int p, int s_
 // already factored and T from `T`, the strips held in registers across the
 // panels.  Done right before block b is factored, so that block b depends on
 // nothing that a predecessor task writes later than its own block b.
-template <int NB, int KIND>
-__device__ __forceinline__ void panel_left_update(double* A, double* R, const double* T, int b) {
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void panel_left_update(E* A, E* R, const E* T, int b) {
   constexpr int NRB = NB / 16;
   b = __builtin_amdgcn_readfirstlane(b);
-  Smem<NB>& sm = smem<NB>();
+  Smem<E, NB>& sm = smem<E, NB>();
   const Lane L;
   const int np = 4 * b;  // panels applied
   const bool on = L.wave < 4;
@@ -638,21 +698,21 @@ __device__ __forceinline__ void panel_left_update(double* A, double* R, const do
   // row blocks the panels touch: UNM and TS all, TT rows < 16 np (below them,
   // a TT victim holds its own GEQRT reflectors)
   const int hi = (KIND == K_TT) ? np - 1 : NRB - 1;
-  double* strip = A + (int64_t)(16 * s) * NB;
-  d4 acc[NRB];
+  E* strip = A + (int64_t)(16 * s) * NB;
+  V4<E> acc[NRB];
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb)
-    if (on && rb <= hi) acc[rb] = ld4(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB);
-  PanelPrefetch<NB> pf;
-  prefetch_panel<NB, KIND>(pf, A, NB, T, 0);
+    if (on && rb <= hi) acc[rb] = ld4<E>(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB);
+  PanelPrefetch<E, NB> pf;
+  prefetch_panel<E, NB, KIND>(pf, A, NB, T, 0);
   for (int p = 0; p < np; ++p) {
-    double* Vs = sm.V[p & 1];
-    double* Ts = sm.T[p & 1];
-    stage_panel<NB, KIND>(pf, Vs, Ts, p);
+    E* Vs = sm.V[p & 1];
+    E* Ts = sm.T[p & 1];
+    stage_panel<E, NB, KIND>(pf, Vs, Ts, p);
     lds_barrier();
-    if (p + 1 < np) prefetch_panel<NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
+    if (p + 1 < np) prefetch_panel<E, NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
     if (on)
-      apply_panel<NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
+      apply_panel<E, NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
   }
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb)
@@ -726,9 +786,9 @@ __device__ __forceinline__ int32_t* counter(const LaunchArgs& a, int r, int c, i
 
 // Takes the next task index (uniform), or -1 when every task has been
 // handed out or the launch was aborted.
-template <int NB>
+template <typename E, int NB>
 __device__ __noinline__ int take_task(const LaunchArgs& a) {
-  Smem<NB>& sm = smem<NB>();
+  Smem<E, NB>& sm = smem<E, NB>();
   if (threadIdx.x == 0) {
     int t = -1;
     // an aborted launch hands out no more tasks: every workgroup leaves at
@@ -756,9 +816,9 @@ __device__ __noinline__ int take_task(const LaunchArgs& a) {
 
 // Thread 0 waits for the task's input versions (panel tasks: block 0);
 // returns 1 (uniform) when they were reached, 0 when the launch was aborted.
-template <int NB>
+template <typename E, int NB>
 __device__ __noinline__ int wait_task(const LaunchArgs& a, int t, const DevTask& task) {
-  Smem<NB>& sm = smem<NB>();
+  Smem<E, NB>& sm = smem<E, NB>();
   if (threadIdx.x == 0) {
     const int op = task.op, i = task.row, piv = task.killer, k = task.k, j = task.j;
     int64_t spins = 0;
@@ -804,9 +864,9 @@ __device__ __noinline__ int wait_task(const LaunchArgs& a, int t, const DevTask&
 }
 
 // Panel tasks, inside the task: wait for block b (b >= 1) of the tile(s).
-template <int NB>
+template <typename E, int NB>
 __device__ __noinline__ int wait_block(const LaunchArgs& a, int t, const DevTask& task, int b) {
-  Smem<NB>& sm = smem<NB>();
+  Smem<E, NB>& sm = smem<E, NB>();
   __syncthreads();
   if (threadIdx.x == 0) {
     int64_t spins = 0;
@@ -825,7 +885,7 @@ __device__ __noinline__ int wait_block(const LaunchArgs& a, int t, const DevTask
 }
 
 // Panel tasks, inside the task: block b of the tile(s) is final.
-template <int NB>
+template <typename E, int NB>
 __device__ __noinline__ void release_block(const LaunchArgs& a, const DevTask& task, int b) {
   stores_done();
   __syncthreads();
@@ -839,7 +899,7 @@ __device__ __noinline__ void release_block(const LaunchArgs& a, const DevTask& t
 // Publishes the task's tile writes and bumps the counters of the tiles it
 // wrote (panel tasks: the last active block; the others went out with
 // release_block).
-template <int NB>
+template <typename E, int NB>
 __device__ __noinline__ void finish_task(const LaunchArgs& a, int t, const DevTask& task) {
   stores_done();
   __syncthreads();
@@ -878,12 +938,14 @@ __device__ __noinline__ void finish_task(const LaunchArgs& a, int t, const DevTa
 
 // Tiles are stored contiguously (tile (r, c) at index c * mt + r, each one
 // column-major with leading dimension nb), so a tile spans a few pages only.
-__device__ __forceinline__ double* tile_ptr(const LaunchArgs& a, int nb, int r, int c) {
-  return a.A + ((int64_t)c * a.mt + r) * nb * nb;
+template <typename E>
+__device__ __forceinline__ E* tile_ptr(const LaunchArgs& a, int nb, int r, int c) {
+  return (E*)a.A + ((int64_t)c * a.mt + r) * nb * nb;
 }
 
-__device__ __forceinline__ double* t_block(double* T, const LaunchArgs& a, int nb, int r, int c) {
-  return T + ((int64_t)r * a.nt + c) * nb * 16;
+template <typename E>
+__device__ __forceinline__ E* t_block(void* T, const LaunchArgs& a, int nb, int r, int c) {
+  return (E*)T + ((int64_t)r * a.nt + c) * nb * 16;
 }
 
 // One tile kernel per function (each gets its own register allocation).
@@ -893,25 +955,25 @@ __device__ __forceinline__ double* t_block(double* T, const LaunchArgs& a, int n
 // takes this task's earlier panels, is factored, and is published at once
 // (except the last active block, published by finish_task).  Returns 0 when
 // the launch was aborted while waiting.
-template <int NB, int KIND>
+template <typename E, int NB, int KIND>
 __device__ __noinline__ int panel_task(const LaunchArgs& a, int t, const DevTask& task) {
-  double* T = t_block((KIND == K_UNM) ? a.Tg : a.Tk, a, NB, task.row, task.k);
-  double* A = tile_ptr(a, NB, task.row, task.k);
-  double* R = KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.k);
+  E* T = t_block<E>((KIND == K_UNM) ? a.Tg : a.Tk, a, NB, task.row, task.k);
+  E* A = tile_ptr<E>(a, NB, task.row, task.k);
+  E* R = KIND == K_UNM ? nullptr : tile_ptr<E>(a, NB, task.killer, task.k);
   const int active = task.chunk;  // blocks holding matrix columns
   __builtin_amdgcn_s_setprio(2);
   for (int b = 0; b < NB / 64; ++b) {
-    if (b > 0 && b < active && !wait_block<NB>(a, t, task, b)) {
+    if (b > 0 && b < active && !wait_block<E, NB>(a, t, task, b)) {
       __builtin_amdgcn_s_setprio(0);
       return 0;
     }
-    if (b > 0) panel_left_update<NB, KIND>(A, R, T, b);
+    if (b > 0) panel_left_update<E, NB, KIND>(A, R, T, b);
     for (int p = 4 * b; p < 4 * b + 4; ++p) {
-      panel_columns<NB, KIND>(A, R, T, p);
-      if (p < 4 * b + 3) panel_strips<NB, KIND>(A, R, p, 4 * b + 3);
+      panel_columns<E, NB, KIND>(A, R, T, p);
+      if (p < 4 * b + 3) panel_strips<E, NB, KIND>(A, R, p, 4 * b + 3);
     }
     if (b + 1 < active) {
-      release_block<NB>(a, task, b);
+      release_block<E, NB>(a, task, b);
     } else {
       stores_done();
       __syncthreads();  // the next block reads the columns and T stored by this one
@@ -923,32 +985,34 @@ __device__ __noinline__ int panel_task(const LaunchArgs& a, int t, const DevTask
 
 // An update task covers one or two 64-column sub-chunks (one 16-column
 // strip per wave; one sub-chunk at nb = 64 and at the ragged end of a tile).
-template <int NB, int KIND>
+template <typename E, int NB, int KIND>
 __device__ __noinline__ void update_task(const LaunchArgs& a, const DevTask& task) {
-  double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
+  void* T = (KIND == K_UNM) ? a.Tg : a.Tk;
   const int64_t colchunk = (int64_t)task.chunk * 64 * NB;
-  const double* V = tile_ptr(a, NB, task.row, task.k);
-  const double* Tb = t_block(T, a, NB, task.row, task.k);
-  double* C1 = KIND == K_UNM ? nullptr : tile_ptr(a, NB, task.killer, task.j) + colchunk;
-  double* C2 = tile_ptr(a, NB, task.row, task.j) + colchunk;
+  const E* V = tile_ptr<E>(a, NB, task.row, task.k);
+  const E* Tb = t_block<E>(T, a, NB, task.row, task.k);
+  E* C1 = KIND == K_UNM ? nullptr : tile_ptr<E>(a, NB, task.killer, task.j) + colchunk;
+  E* C2 = tile_ptr<E>(a, NB, task.row, task.j) + colchunk;
   if (NB >= 128 && (task.pad >> 8) == 2)
-    run_update<NB, KIND, true, 128>(smem<NB>(), V, Tb, C1, C2, NB);
+    run_update<E, NB, KIND, true, 128>(smem<E, NB>(), V, Tb, C1, C2, NB);
   else
-    run_update<NB, KIND, true, 64>(smem<NB>(), V, Tb, C1, C2, NB);
+    run_update<E, NB, KIND, true, 64>(smem<E, NB>(), V, Tb, C1, C2, NB);
 }
 
 // Block of 64 columns of B (nb x 64, column-major) of tile row r.
-__device__ __forceinline__ double* b_block(const LaunchArgs& a, int nb, int r, int j) {
-  return a.B + ((int64_t)j * a.mt + r) * nb * 64;
+template <typename E>
+__device__ __forceinline__ E* b_block(const LaunchArgs& a, int nb, int r, int j) {
+  return (E*)a.B + ((int64_t)j * a.mt + r) * nb * 64;
 }
 
 // The same transformation applied to a block of B (hqr_apply_qt/_q).
-template <int NB, int KIND, bool TRANS>
+template <typename E, int NB, int KIND, bool TRANS>
 __device__ __noinline__ void apply_task(const LaunchArgs& a, const DevTask& task) {
-  double* T = (KIND == K_UNM) ? a.Tg : a.Tk;
-  run_update<NB, KIND, TRANS, 64>(smem<NB>(), tile_ptr(a, NB, task.row, task.k), t_block(T, a, NB, task.row, task.k),
-                                 KIND == K_UNM ? nullptr : b_block(a, NB, task.killer, task.j),
-                                 b_block(a, NB, task.row, task.j), NB);
+  void* T = (KIND == K_UNM) ? a.Tg : a.Tk;
+  run_update<E, NB, KIND, TRANS, 64>(smem<E, NB>(), tile_ptr<E>(a, NB, task.row, task.k),
+                                     t_block<E>(T, a, NB, task.row, task.k),
+                                     KIND == K_UNM ? nullptr : b_block<E>(a, NB, task.killer, task.j),
+                                     b_block<E>(a, NB, task.row, task.j), NB);
 }
 
 // Points the per-problem fields of `la` (tiles, T factors, counters, tile
@@ -972,43 +1036,43 @@ __device__ __forceinline__ void bind_problem(LaunchArgs& la, const LaunchArgs& a
 // Every task a workgroup waits for was taken earlier by a running
 // workgroup, so the wait always ends.  BATCH: the tasks of many independent
 // problems share the cursor (each task names its problem).
-template <int NB, bool BATCH>
+template <typename E, int NB, bool BATCH>
 __global__ __launch_bounds__(NT, 1) void persistent_kernel(LaunchArgs args) {
   LaunchArgs la = args;
   for (;;) {
-    const int t = take_task<NB>(args);
+    const int t = take_task<E, NB>(args);
     if (t < 0) break;
     const DevTask task = args.tasks[t];
     if (BATCH) bind_problem(la, args, t);
     const LaunchArgs& a = BATCH ? la : args;
-    if (!wait_task<NB>(a, t, task)) break;
+    if (!wait_task<E, NB>(a, t, task)) break;
     int ok = 1;
     if (a.B) {
       if (a.trans) {
         switch (task.op) {
-          case UNMQR: apply_task<NB, K_UNM, true>(a, task); break;
-          case TSMQR: apply_task<NB, K_TS, true>(a, task); break;
-          default: apply_task<NB, K_TT, true>(a, task); break;
+          case UNMQR: apply_task<E, NB, K_UNM, true>(a, task); break;
+          case TSMQR: apply_task<E, NB, K_TS, true>(a, task); break;
+          default: apply_task<E, NB, K_TT, true>(a, task); break;
         }
       } else {
         switch (task.op) {
-          case UNMQR: apply_task<NB, K_UNM, false>(a, task); break;
-          case TSMQR: apply_task<NB, K_TS, false>(a, task); break;
-          default: apply_task<NB, K_TT, false>(a, task); break;
+          case UNMQR: apply_task<E, NB, K_UNM, false>(a, task); break;
+          case TSMQR: apply_task<E, NB, K_TS, false>(a, task); break;
+          default: apply_task<E, NB, K_TT, false>(a, task); break;
         }
       }
     } else {
       switch (task.op) {
-        case GEQRT: ok = panel_task<NB, K_UNM>(a, t, task); break;
-        case TSQRT: ok = panel_task<NB, K_TS>(a, t, task); break;
-        case TTQRT: ok = panel_task<NB, K_TT>(a, t, task); break;
-        case UNMQR: update_task<NB, K_UNM>(a, task); break;
-        case TSMQR: update_task<NB, K_TS>(a, task); break;
-        default: update_task<NB, K_TT>(a, task); break;
+        case GEQRT: ok = panel_task<E, NB, K_UNM>(a, t, task); break;
+        case TSQRT: ok = panel_task<E, NB, K_TS>(a, t, task); break;
+        case TTQRT: ok = panel_task<E, NB, K_TT>(a, t, task); break;
+        case UNMQR: update_task<E, NB, K_UNM>(a, task); break;
+        case TSMQR: update_task<E, NB, K_TS>(a, task); break;
+        default: update_task<E, NB, K_TT>(a, task); break;
       }
     }
     if (!ok) break;  // aborted inside a panel task
-    finish_task<NB>(a, t, task);
+    finish_task<E, NB>(a, t, task);
   }
 }
 
@@ -1026,21 +1090,25 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
 // B).  `in` fills the blocks and zeroes the padding beyond M and N; `out`
 // copies the M x N part back.  One thread per element of the padded matrix,
 // rows fastest.
-__device__ __forceinline__ void tile_copy_elem(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb,
-                                               int tw, int mt, int64_t x, int in) {
+// The matrix holds S elements, the blocks E elements (a float copy of a
+// double matrix rounds each element to nearest).
+template <typename S, typename E>
+__device__ __forceinline__ void tile_copy_elem(S* A, int64_t lda, E* At, int64_t M, int64_t N, int nb, int tw,
+                                               int mt, int64_t x, int in) {
   const int64_t Mp = (int64_t)mt * nb;
   const int64_t r = x % Mp, c = x / Mp;
   const int64_t i = r / nb, j = c / tw;
-  double* t = At + ((j * mt + i) * tw + (c - j * tw)) * nb + (r - i * nb);
+  E* t = At + ((j * mt + i) * tw + (c - j * tw)) * nb + (r - i * nb);
   const bool inside = r < M && c < N;
   if (in)
-    *t = inside ? A[r + c * lda] : 0.0;
+    *t = inside ? (E)A[r + c * lda] : E(0);
   else if (inside)
-    A[r + c * lda] = *t;
+    A[r + c * lda] = (S)*t;
 }
 
-__global__ void tile_copy_kernel(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int tw, int mt,
-                                 int nt, int in) {
+template <typename S, typename E>
+__global__ void tile_copy_kernel(S* A, int64_t lda, E* At, int64_t M, int64_t N, int nb, int tw, int mt, int nt,
+                                 int in) {
   const int64_t total = (int64_t)mt * nb * (int64_t)nt * tw;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x)
     tile_copy_elem(A, lda, At, M, N, nb, tw, mt, x, in);
@@ -1058,9 +1126,9 @@ __global__ void copy_batched_kernel(const ProbDesc* descs, char* w, int nb, int 
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < ta + tb;
        x += (int64_t)gridDim.x * blockDim.x) {
     if (x < ta)
-      tile_copy_elem(d->A, d->lda, At, d->M, d->N, nb, nb, d->mt, x, in);
+      tile_copy_elem<double, double>(d->A, d->lda, At, d->M, d->N, nb, nb, d->mt, x, in);
     else
-      tile_copy_elem(d->B, d->ldb, Bt, d->M, d->nrhs, nb, nb, d->mt, x - ta, in);
+      tile_copy_elem<double, double>(d->B, d->ldb, Bt, d->M, d->nrhs, nb, nb, d->mt, x - ta, in);
   }
 }
 
@@ -1076,17 +1144,17 @@ __global__ void copy_batched_kernel(const ProbDesc* descs, char* w, int nb, int 
 //   16 x 16 diagonal block (lane = column), the rows above subtract it.
 // A zero diagonal entry R_jj is recorded in ctrl (status HQR_ERR_SINGULAR,
 // *info = max over such j of N - j; nword, when not null, receives N).
-template <int NB>
-__device__ void trsm_tile_row(const double* R, double* Y, int cpt, int32_t* ctrl, int32_t* info, int32_t* nword,
+template <typename E, int NB>
+__device__ void trsm_tile_row(const E* R, E* Y, int cpt, int32_t* ctrl, int32_t* info, int32_t* nword,
                               int64_t N, int mt, int nt, int i, int blk, int grp) {
-  double* xs = hqr_lds;  // x_j or z of this tile row: NB rows x 16 columns, stride 17 (dynamic LDS)
+  E* xs = reinterpret_cast<E*>(hqr_lds);  // x_j or z of this tile row: NB rows x 16 columns, stride 17 (dynamic LDS)
   const int r = threadIdx.x;
   const int64_t row0 = (int64_t)i * NB;
   const int nv = (int)((N - row0) < NB ? (N - row0) : NB);  // rows of this tile row inside N
   // Y: tile columns of 64 cpt columns; block blk = chunk blk % cpt of tile column blk / cpt
   const int64_t rstride = (int64_t)NB * 64 * cpt;  // from one tile row of Y to the next
-  double* Yb = Y + (int64_t)(blk / cpt) * mt * rstride + (int64_t)(64 * (blk % cpt) + 16 * grp) * NB;
-  double z[16];
+  E* Yb = Y + (int64_t)(blk / cpt) * mt * rstride + (int64_t)(64 * (blk % cpt) + 16 * grp) * NB;
+  E z[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) z[c] = Yb[(int64_t)i * rstride + r + (int64_t)c * NB];
   for (int j = i + 1; j < nt; ++j) {
@@ -1094,18 +1162,18 @@ __device__ void trsm_tile_row(const double* R, double* Y, int cpt, int32_t* ctrl
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      const double xv = Yb[(int64_t)j * rstride + r + (int64_t)c * NB];
-      xs[r * 17 + c] = (jrow0 + r < N) ? xv : 0.0;
+      const E xv = Yb[(int64_t)j * rstride + r + (int64_t)c * NB];
+      xs[r * 17 + c] = (jrow0 + r < N) ? xv : E(0);
     }
     __syncthreads();
-    const double* Rij = R + ((int64_t)j * mt + i) * NB * NB + r;
+    const E* Rij = R + ((int64_t)j * mt + i) * NB * NB + r;
     for (int k = 0; k < NB; ++k) {
-      const double rk = Rij[(int64_t)k * NB];
+      const E rk = Rij[(int64_t)k * NB];
 #pragma unroll
       for (int c = 0; c < 16; ++c) z[c] -= rk * xs[k * 17 + c];
     }
   }
-  const double* Rii = R + ((int64_t)i * mt + i) * NB * NB;
+  const E* Rii = R + ((int64_t)i * mt + i) * NB * NB;
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < 16; ++c) xs[r * 17 + c] = z[c];
@@ -1116,10 +1184,10 @@ __device__ void trsm_tile_row(const double* R, double* Y, int cpt, int32_t* ctrl
       const int c = r;  // lane = column
       for (int rr = r0 + 15; rr >= r0; --rr) {
         if (rr >= nv) continue;
-        double t = xs[rr * 17 + c];
+        E t = xs[rr * 17 + c];
         for (int k = rr + 1; k < r0 + 16 && k < nv; ++k) t -= Rii[rr + (int64_t)k * NB] * xs[k * 17 + c];
-        const double d = Rii[rr + (int64_t)rr * NB];
-        if (d == 0.0 && c == 0) {
+        const E d = Rii[rr + (int64_t)rr * NB];
+        if (d == E(0) && c == 0) {
           int32_t none = 0;
           __hip_atomic_compare_exchange_strong(&ctrl[1], &none, (int32_t)HQR_ERR_SINGULAR, __ATOMIC_RELAXED,
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1133,7 +1201,7 @@ __device__ void trsm_tile_row(const double* R, double* Y, int cpt, int32_t* ctrl
     if (r < r0) {
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
-        double t = xs[r * 17 + c];
+        E t = xs[r * 17 + c];
         for (int k = r0; k < r0 + 16 && k < nv; ++k) t -= Rii[r + (int64_t)k * NB] * xs[k * 17 + c];
         xs[r * 17 + c] = t;
       }
@@ -1148,10 +1216,10 @@ __device__ void trsm_tile_row(const double* R, double* Y, int cpt, int32_t* ctrl
 
 // Tile row i of one problem; workgroup x = (64-column block, group of 16).
 // A zero diagonal entry sets ctrl[6] = max(N - j) and ctrl[7] = N.
-template <int NB>
-__global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const double* R, double* Y, int cpt, int32_t* ctrl,
+template <typename E, int NB>
+__global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const E* R, E* Y, int cpt, int32_t* ctrl,
                                                            int64_t N, int mt, int nt, int i, int groups) {
-  trsm_tile_row<NB>(R, Y, cpt, ctrl, &ctrl[6], &ctrl[7], N, mt, nt, i, blockIdx.x / groups, blockIdx.x % groups);
+  trsm_tile_row<E, NB>(R, Y, cpt, ctrl, &ctrl[6], &ctrl[7], N, mt, nt, i, blockIdx.x / groups, blockIdx.x % groups);
 }
 
 // Every tile row of every problem of a batch in one launch: workgroup
@@ -1168,8 +1236,8 @@ __global__ __launch_bounds__(NB) void trsm_batched_kernel(const ProbDesc* descs,
   const double* R = (const double*)(w + d->tiles);
   double* Y = (double*)(w + d->tiles) + (int64_t)d->mt * d->nt * NB * NB;
   for (int i = d->nt - 1; i >= 0; --i) {
-    trsm_tile_row<NB>(R, Y, NB / 64, ctrl, info + blockIdx.y, nullptr, d->N, d->mt, d->nt, i,
-                      (int)blockIdx.x / groups, (int)blockIdx.x % groups);
+    trsm_tile_row<double, NB>(R, Y, NB / 64, ctrl, info + blockIdx.y, nullptr, d->N, d->mt, d->nt, i,
+                              (int)blockIdx.x / groups, (int)blockIdx.x % groups);
     __syncthreads();  // the rows of x just stored are read by the next tile rows
   }
 }
@@ -1198,36 +1266,64 @@ int launch_zero_i32(int32_t* p, int64_t n, void* stream) {
   return record_hip(hipGetLastError(), "zero_i32_kernel launch");
 }
 
-int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int tw, int mt, int nt,
-                     bool in, void* stream) {
+int launch_tile_copy(void* A, int a_f32, int64_t lda, void* At, int at_f32, int64_t M, int64_t N, int nb, int tw,
+                     int mt, int nt, bool in, void* stream) {
   const int64_t total = (int64_t)mt * nb * (int64_t)nt * tw;
-  hipLaunchKernelGGL(tile_copy_kernel, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, A, lda, At, M, N, nb,
-                     tw, mt, nt, in ? 1 : 0);
+  const dim3 g(grid_for(total)), b(256);
+  hipStream_t s = (hipStream_t)stream;
+  const int i = in ? 1 : 0;
+  if (!a_f32 && !at_f32)
+    hipLaunchKernelGGL((tile_copy_kernel<double, double>), g, b, 0, s, (double*)A, lda, (double*)At, M, N, nb, tw, mt,
+                       nt, i);
+  else if (!a_f32 && at_f32)
+    hipLaunchKernelGGL((tile_copy_kernel<double, float>), g, b, 0, s, (double*)A, lda, (float*)At, M, N, nb, tw, mt,
+                       nt, i);
+  else if (a_f32 && at_f32)
+    hipLaunchKernelGGL((tile_copy_kernel<float, float>), g, b, 0, s, (float*)A, lda, (float*)At, M, N, nb, tw, mt, nt,
+                       i);
+  else
+    return HQR_ERR_INTERNAL;
   return record_hip(hipGetLastError(), "tile_copy_kernel launch");
 }
 
-int launch_trsm(int nb, const double* R, double* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
-                int groups, void* stream) {
+int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int tw, int mt, int nt,
+                     bool in, void* stream) {
+  return launch_tile_copy(A, 0, lda, At, 0, M, N, nb, tw, mt, nt, in, stream);
+}
+
+template <typename E>
+static int launch_trsm_t(int nb, const E* R, E* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
+                         int groups, void* stream) {
   for (int i = nt - 1; i >= 0; --i) {
     const dim3 grid(nbc * groups), block(nb);
-    const size_t lds = (size_t)nb * 17 * sizeof(double);
+    const size_t lds = (size_t)nb * 17 * sizeof(E);
     switch (nb) {
       case 64:
-        hipLaunchKernelGGL(trsm_tile_row_kernel<64>, grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N, mt, nt,
-                           i, groups);
+        hipLaunchKernelGGL((trsm_tile_row_kernel<E, 64>), grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N,
+                           mt, nt, i, groups);
         break;
       case 128:
-        hipLaunchKernelGGL(trsm_tile_row_kernel<128>, grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N, mt,
-                           nt, i, groups);
+        hipLaunchKernelGGL((trsm_tile_row_kernel<E, 128>), grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N,
+                           mt, nt, i, groups);
         break;
       default:
-        hipLaunchKernelGGL(trsm_tile_row_kernel<256>, grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N, mt,
-                           nt, i, groups);
+        hipLaunchKernelGGL((trsm_tile_row_kernel<E, 256>), grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N,
+                           mt, nt, i, groups);
         break;
     }
     if (int rc = record_hip(hipGetLastError(), "trsm_tile_row_kernel launch")) return rc;
   }
   return 0;
+}
+
+int launch_trsm(int nb, const double* R, double* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
+                int groups, void* stream) {
+  return launch_trsm_t<double>(nb, R, Y, cpt, ctrl, N, mt, nt, nbc, groups, stream);
+}
+
+int launch_trsm_f32(int nb, const float* R, float* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
+                    int groups, void* stream) {
+  return launch_trsm_t<float>(nb, R, Y, cpt, ctrl, N, mt, nt, nbc, groups, stream);
 }
 
 int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, void* stream) {
@@ -1250,45 +1346,59 @@ int launch_trsm_batched(int nb, const ProbDesc* d, char* w, int32_t* ctrl, int32
   return record_hip(hipGetLastError(), "trsm_batched_kernel launch");
 }
 
-template <int NB>
+template <typename E, int NB>
 static int occupancy_workers() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_kernel<NB, false>, NT, sizeof(Smem<NB>)) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_kernel<E, NB, false>, NT, sizeof(Smem<E, NB>)) != hipSuccess ||
       per < 1)
     per = 1;
   return cus * per;
 }
 
-int default_workers(int nb) {
+int default_workers(int nb, bool f32) {
+  if (f32) {
+    switch (nb) {
+      case 64: return occupancy_workers<float, 64>();
+      case 128: return occupancy_workers<float, 128>();
+      default: return occupancy_workers<float, 256>();
+    }
+  }
   switch (nb) {
-    case 64: return occupancy_workers<64>();
-    case 128: return occupancy_workers<128>();
-    default: return occupancy_workers<256>();
+    case 64: return occupancy_workers<double, 64>();
+    case 128: return occupancy_workers<double, 128>();
+    default: return occupancy_workers<double, 256>();
   }
 }
 
-int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream) {
-  if (workers < 1) workers = 1;
-  hipStream_t s = (hipStream_t)stream;
+template <typename E>
+static int launch_persistent_t(int nb, const LaunchArgs& a, int workers, hipStream_t s) {
   const dim3 g(workers), b(NT);
   if (a.probs) {
     switch (nb) {
-      case 64: hipLaunchKernelGGL((persistent_kernel<64, true>), g, b, sizeof(Smem<64>), s, a); break;
-      case 128: hipLaunchKernelGGL((persistent_kernel<128, true>), g, b, sizeof(Smem<128>), s, a); break;
-      case 256: hipLaunchKernelGGL((persistent_kernel<256, true>), g, b, sizeof(Smem<256>), s, a); break;
+      case 64: hipLaunchKernelGGL((persistent_kernel<E, 64, true>), g, b, sizeof(Smem<E, 64>), s, a); break;
+      case 128: hipLaunchKernelGGL((persistent_kernel<E, 128, true>), g, b, sizeof(Smem<E, 128>), s, a); break;
+      case 256: hipLaunchKernelGGL((persistent_kernel<E, 256, true>), g, b, sizeof(Smem<E, 256>), s, a); break;
       default: return HQR_ERR_INTERNAL;
     }
   } else {
     switch (nb) {
-      case 64: hipLaunchKernelGGL((persistent_kernel<64, false>), g, b, sizeof(Smem<64>), s, a); break;
-      case 128: hipLaunchKernelGGL((persistent_kernel<128, false>), g, b, sizeof(Smem<128>), s, a); break;
-      case 256: hipLaunchKernelGGL((persistent_kernel<256, false>), g, b, sizeof(Smem<256>), s, a); break;
+      case 64: hipLaunchKernelGGL((persistent_kernel<E, 64, false>), g, b, sizeof(Smem<E, 64>), s, a); break;
+      case 128: hipLaunchKernelGGL((persistent_kernel<E, 128, false>), g, b, sizeof(Smem<E, 128>), s, a); break;
+      case 256: hipLaunchKernelGGL((persistent_kernel<E, 256, false>), g, b, sizeof(Smem<E, 256>), s, a); break;
       default: return HQR_ERR_INTERNAL;
     }
   }
   return record_hip(hipGetLastError(), "persistent_kernel launch");
+}
+
+int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream, bool f32) {
+  if (workers < 1) workers = 1;
+  // the batched path runs in FP64 only
+  if (f32 && a.probs) return HQR_ERR_INTERNAL;
+  return f32 ? launch_persistent_t<float>(nb, a, workers, (hipStream_t)stream)
+             : launch_persistent_t<double>(nb, a, workers, (hipStream_t)stream);
 }
 
 }  // namespace hqr

@@ -28,7 +28,8 @@ struct Layout {
 // kernels (one nb x 16 block column per tile and kind) and the
 // tile-contiguous copy of the matrix the factorization works on, followed
 // (hqr_lstsq) by nrhs right-hand-side columns as further tile columns.
-inline Layout layout_for(int64_t M, int64_t N, const hqr_params& p, int64_t nrhs = 0) {
+// esize: bytes per element of the tiles and T factors (8: FP64, 4: FP32).
+inline Layout layout_for(int64_t M, int64_t N, const hqr_params& p, int64_t nrhs = 0, size_t esize = sizeof(double)) {
   Layout L{};
   L.mt = (int32_t)((M + p.nb - 1) / p.nb);
   L.nt = (int32_t)((N + p.nb - 1) / p.nb);
@@ -40,9 +41,9 @@ inline Layout layout_for(int64_t M, int64_t N, const hqr_params& p, int64_t nrhs
   size_t off = 0;
   L.ctrl = off; off = align256(off + kCtrlWords * sizeof(int32_t));
   L.cnt = off; off = align256(off + all * L.chunks * sizeof(int32_t));
-  L.tg = off; off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
-  L.tk = off; off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
-  L.tiles = off; off = align256(off + all * (size_t)p.nb * p.nb * sizeof(double));
+  L.tg = off; off = align256(off + tiles * (size_t)p.nb * 16 * esize);
+  L.tk = off; off = align256(off + tiles * (size_t)p.nb * 16 * esize);
+  L.tiles = off; off = align256(off + all * (size_t)p.nb * p.nb * esize);
   L.total = off;
   return L;
 }

@@ -59,13 +59,20 @@ int launch_zero_i32(int32_t* p, int64_t n, void* stream);
 
 // Run every task of the plan in one persistent launch of `workers`
 // workgroups.  nb is 64, 128 or 256.
-int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream);
+// f32: the tiles, T factors and B blocks hold float and the tile kernels
+// run in FP32 (single-problem launches only).
+int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream, bool f32 = false);
 
 // Copies the column-major M x N matrix A (leading dimension lda) into the
 // blocked buffer At (mt x nt blocks of nb rows x tw columns, zero padding
 // beyond M and N) when `in`, or the M x N part of At back into A otherwise.
 int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, int nb, int tw, int mt, int nt,
                      bool in, void* stream);
+// The same with the element type of each side chosen: a_f32 / at_f32 = 1
+// for float (double -> float copies round to nearest; float -> double is
+// not offered for the matrix side).
+int launch_tile_copy(void* A, int a_f32, int64_t lda, void* At, int at_f32, int64_t M, int64_t N, int nb, int tw,
+                     int mt, int nt, bool in, void* stream);
 
 // Back substitution with the leading N x N triangle of the factored tiles R
 // on the first N rows of Y (tile columns of nb rows x 64 cpt columns; nbc
@@ -73,6 +80,8 @@ int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, i
 // tile row by tile row.
 int launch_trsm(int nb, const double* R, double* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
                 int groups, void* stream);
+int launch_trsm_f32(int nb, const float* R, float* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
+                    int groups, void* stream);
 
 // Stores "where: message" of a failed HIP call for hqr_last_error(); returns
 // HQR_ERR_HIP on failure, 0 on success.
@@ -89,6 +98,6 @@ int launch_trsm_batched(int nb, const ProbDesc* d, char* w, int32_t* ctrl, int32
                         void* stream);
 
 // Workgroups that fit on the device at once (per CU occupancy x CUs).
-int default_workers(int nb);
+int default_workers(int nb, bool f32 = false);
 
 }  // namespace hqr
