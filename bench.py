@@ -179,7 +179,7 @@ def run_lstsq(device, M=32768, N=2048, seed=4, reps=5):
             times.append(e0.elapsed_time(e1) / 1e3)
     if h.status(work, stream) != 0:
         raise RuntimeError("device status %d in the least-squares workload" % h.status(work, stream))
-    x = b[:N]
+    x = b[:N].clone()
     r_ = b0 - A0 @ x
     # optimality of the computed solution: ||A^T r|| / (||A||^2 ||x||) is of the order of the unit roundoff
     # for a backward-stable solver
@@ -191,7 +191,28 @@ def run_lstsq(device, M=32768, N=2048, seed=4, reps=5):
            "gflops": (qr_flops(M, N) + 4.0 * M * N) / t / 1e9,
            "forward_error_vs_x_true": ((x - xs).norm() / xs.norm()).item(),
            "normal_equations_residual": opt}
-    del A, b, A0, b0, work
+    # the same problem with an FP32 factorization refined in FP64 (hqr_lstsq_ir)
+    pf = h.make_params(nb=256, p=4, a=4, low="greedy", high="fibonacci", domino=1)
+    del A, b, work
+    torch.cuda.empty_cache()
+    out["ir"] = []
+    for tol in (1e-12, 1e-15):
+        tir = []
+        for r in range(3):
+            torch.cuda.synchronize(device)
+            t0 = time.perf_counter()
+            xi, info = h.lstsq_ir(A0, b0.reshape(-1), pf, max_iter=30, tol=tol, stream=stream)
+            torch.cuda.synchronize(device)
+            if r > 0:
+                tir.append(time.perf_counter() - t0)
+        ti = sum(tir) / len(tir)
+        out["ir"].append({
+            "method": "FP32 tiled QR + FP64 augmented-system refinement, stop at backward error <= %g" % tol,
+            "ms_per_solve": 1e3 * ti, "solves_per_s": 1.0 / ti, "iterations": info["iterations"],
+            "converged": info["converged"], "eta": info["eta"],
+            "forward_error_vs_x_true": ((xi - xs.reshape(-1)).norm() / xs.norm()).item(),
+            "difference_vs_fp64_solution": ((xi - x.reshape(-1)).norm() / x.norm()).item()})
+    del A0, b0
     torch.cuda.empty_cache()
     return out
 

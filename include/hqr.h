@@ -263,6 +263,46 @@ int hqr_lstsq_workspace_size(int64_t M, int64_t N, int32_t nrhs, const hqr_param
 int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t ldb, int32_t nrhs,
               const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
 
+/* ---- Mixed-precision least squares ----
+ *
+ * min ||A x - b|| for a double A (M x N, M >= N, full rank) and one
+ * right-hand side: A is rounded to float and factored by the FP32 tiled QR
+ * (as hqr_factor_f32); then the augmented system [I A; A^T 0][r; x] = [b; 0]
+ * is refined (Bjorck's iterative refinement for least squares): each
+ * iteration forms f = b - r - A x and g = -A^T r in FP64 from the original
+ * double A, solves the correction with the FP32 factors (Q applied in FP32,
+ * triangular solves with the float R in FP64 arithmetic) and updates x and r
+ * in FP64.  It converges when the condition number of A times the float
+ * unit roundoff (6e-8) is well below 1. */
+typedef struct hqr_ir_info {
+  int32_t iterations;  /* corrections applied (the first one gives the FP32 solution) */
+  int32_t converged;   /* 1 when eta <= tol */
+  double eta;          /* backward error of the returned (x, r), see hqr_lstsq_ir */
+  double history[32];  /* eta before each of the first 32 corrections (history[0] = 1: x = r = 0) */
+} hqr_ir_info;
+
+/* Workspace bytes of hqr_lstsq_ir (FP32 factorization, one FP32 block
+ * column for Q, and FP64 vectors).  Errors: -1 M < 1 or M < N, -2 N < 1, -3
+ * bad params, -4 bytes NULL. */
+int hqr_lstsq_ir_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* bytes);
+
+/* Solves min ||A x - b||: dA (lda >= M) and db (M) are read only; dx (N)
+ * receives x, dr (M, may be NULL) the residual r of the augmented system
+ * (b - A x at convergence).  The iterate is judged by the normwise backward
+ * error of the augmented system, eta = sqrt(||f||^2 + ||g||^2) /
+ * (||A||_F (||x|| + ||r||) + ||b||); the loop stops when eta <= tol, when
+ * a correction did not lower eta, or after max_iter corrections; info (may
+ * be NULL) reports the count and the eta history.  The forward error of x
+ * is about kappa(A) times the final eta: tol near the FP64 unit roundoff
+ * (1e-15) gives FP64 accuracy.  Synchronizes `stream` once per correction (eta is read on the
+ * host).  Errors: -1 dA NULL, -2 M < N or
+ * M < 1, -3 N < 1, -4 lda < M, -5 db NULL, -6 dx NULL, -8 bad params, -9 bad
+ * exec.order, -10 max_iter < 1, -11 tol < 0 or NaN, -12 dwork NULL, -13
+ * dwork too small; HQR_ERR_WATCHDOG if a launch was aborted. */
+int hqr_lstsq_ir(const double* dA, int64_t M, int64_t N, int64_t lda, const double* db, double* dx, double* dr,
+                 const hqr_params* params, const hqr_exec* exec, int32_t max_iter, double tol, void* dwork,
+                 size_t work_bytes, void* stream, hqr_ir_info* info);
+
 /* ---- Batched problems (one persistent launch for many small QRs) ----
  *
  * Many independent factorizations or least-squares solves, each with its own

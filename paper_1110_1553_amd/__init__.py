@@ -7,6 +7,8 @@ this package only marshals arguments to it:
   persistent GPU launch driven by a hierarchical elimination tree;
 * :func:`apply_qt`, :func:`apply_q` -- B <- Q^T B and B <- Q B with a
   finished factorization; :func:`lstsq` -- least squares through both;
+* :func:`lstsq_ir` -- least squares with an FP32 factorization refined to
+  FP64 accuracy (augmented-system iterative refinement);
 * :func:`lstsq_batched`, :class:`BatchedLstsq` -- many independent small
   least-squares problems (or factorizations) in one persistent launch;
 * :func:`elimlist`, :func:`validate`, :func:`dag_stats` -- the elimination
@@ -22,7 +24,7 @@ from ._lib import (BINARY, CHAIN, FIBONACCI, FLAT, GREEDY, OPS, Exec, HQRError, 
 __all__ = ["FLAT", "BINARY", "GREEDY", "FIBONACCI", "CHAIN", "OPS", "Params", "Exec", "HQRError", "make_params",
            "make_exec", "elimlist", "validate", "dag_stats", "workspace_size", "apply_workspace_size",
            "lstsq_workspace_size", "factor",
-           "apply_qt", "apply_q", "lstsq", "lstsq_batched", "BatchedLstsq", "colmajor", "r_of", "Workspace", "ApplyWorkspace", "status",
+           "apply_qt", "apply_q", "lstsq", "lstsq_ir", "lstsq_batched", "BatchedLstsq", "colmajor", "r_of", "Workspace", "ApplyWorkspace", "status",
            "release_plans", "version"]
 
 
@@ -157,6 +159,29 @@ def lstsq(A, B, params, exec_=None, work=None, stream=None, check=True):
     if check:
         _device_status(work, s, "hqr_lstsq")
     return work
+
+
+def lstsq_ir(A, b, params, exec_=None, max_iter=30, tol=1e-12, stream=None, residual=False):
+    """min ||A x - b|| for a column-major float64 CUDA matrix A (M x N) and
+    vector b (M): FP32 factorization plus FP64 refinement (hqr_lstsq_ir).
+    A and b are not modified.  Returns (x, info) or (x, r, info) with
+    ``residual``; info has iterations, converged, eta and history."""
+    import torch
+
+    M, N, lda = _colmajor_args(A, "A")
+    b = b.reshape(-1)
+    if b.dtype != torch.float64 or not b.is_cuda or b.numel() != M or not b.is_contiguous():
+        raise ValueError("b must be a contiguous float64 CUDA vector of length M")
+    x = torch.empty(N, dtype=torch.float64, device=A.device)
+    r = torch.empty(M, dtype=torch.float64, device=A.device) if residual else None
+    nbytes = _lib.lstsq_ir_workspace_size(M, N, params)
+    work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    info = _lib.lstsq_ir_ptr(A.data_ptr(), M, N, lda, b.data_ptr(), x.data_ptr(), r.data_ptr() if residual else 0,
+                             params, exec_, max_iter, tol, work.data_ptr(), nbytes, s.cuda_stream)
+    out = {"iterations": info.iterations, "converged": bool(info.converged), "eta": info.eta,
+           "history": list(info.history[: min(info.iterations, 32)])}
+    return (x, r, out) if residual else (x, out)
 
 
 def status(work, stream=None):

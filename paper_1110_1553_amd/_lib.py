@@ -38,11 +38,17 @@ class DagInfo(ctypes.Structure):
                 ("weight", ctypes.c_int64), ("critical_path", ctypes.c_int64), ("device_tasks", ctypes.c_int64)]
 
 
+class IrInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("eta", ctypes.c_double),
+                ("history", ctypes.c_double * 32)]
+
+
 TASK_DTYPE = np.dtype([("op", "u1"), ("chunk", "u1"), ("row", "<u2"), ("killer", "<u2"), ("k", "<u2"),
                        ("j", "<u2"), ("pad", "<u2"), ("v", "<u4", (3,))])
 
 EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size", "hqr_factor",
-           "hqr_workspace_size_f32", "hqr_factor_f32", "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size", "hqr_lstsq",
+           "hqr_workspace_size_f32", "hqr_factor_f32", "hqr_lstsq_ir_workspace_size", "hqr_lstsq_ir",
+           "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size", "hqr_lstsq",
            "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_timeline", "hqr_version",
            "hqr_batch_create", "hqr_batch_workspace_size", "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run",
            "hqr_batch_status", "hqr_batch_destroy", "hqr_lstsq_batched", "hqr_lstsq_batched_workspace_size")
@@ -75,6 +81,9 @@ def load():
     lib.hqr_workspace_size_f32.argtypes = [i64, i64, P(Params), P(ctypes.c_size_t)]
     lib.hqr_factor_f32.argtypes = [vp, i64, i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
     lib.hqr_apply_workspace_size.argtypes = [i64, i32, P(Params), P(ctypes.c_size_t)]
+    lib.hqr_lstsq_ir_workspace_size.argtypes = [i64, i64, P(Params), P(ctypes.c_size_t)]
+    lib.hqr_lstsq_ir.argtypes = [vp, i64, i64, i64, vp, vp, vp, P(Params), P(Exec), i32, ctypes.c_double, vp,
+                                 ctypes.c_size_t, vp, P(IrInfo)]
     apply_args = [i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp, i64, i32, vp, ctypes.c_size_t, vp]
     lib.hqr_apply_qt.argtypes = apply_args
     lib.hqr_apply_q.argtypes = apply_args
@@ -104,7 +113,8 @@ def load():
     lib.hqr_version.restype = ctypes.c_char_p
     for name in ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_stats", "hqr_workspace_size",
                  "hqr_factor", "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size",
-                 "hqr_lstsq", "hqr_status", "hqr_status_ex", "hqr_workspace_size_f32", "hqr_factor_f32", "hqr_batch_create", "hqr_batch_workspace_size",
+                 "hqr_lstsq", "hqr_status", "hqr_status_ex", "hqr_workspace_size_f32", "hqr_factor_f32",
+                 "hqr_lstsq_ir_workspace_size", "hqr_lstsq_ir", "hqr_batch_create", "hqr_batch_workspace_size",
                  "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run", "hqr_batch_status", "hqr_lstsq_batched",
                  "hqr_lstsq_batched_workspace_size"):
         getattr(lib, name).restype = ctypes.c_int
@@ -195,6 +205,24 @@ def factor_f32_ptr(dA: int, M: int, N: int, lda: int, params: Params, exec_: Exe
                                ctypes.byref(exec_) if exec_ is not None else None,
                                ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(stream))
     _check("hqr_factor_f32", rc)
+
+
+def lstsq_ir_workspace_size(M: int, N: int, params: Params) -> int:
+    n = ctypes.c_size_t()
+    _check("hqr_lstsq_ir_workspace_size", load().hqr_lstsq_ir_workspace_size(M, N, ctypes.byref(params),
+                                                                           ctypes.byref(n)))
+    return n.value
+
+
+def lstsq_ir_ptr(dA: int, M: int, N: int, lda: int, db: int, dx: int, dr: int, params: Params, exec_: Exec,
+                 max_iter: int, tol: float, dwork: int, work_bytes: int, stream: int) -> IrInfo:
+    info = IrInfo()
+    rc = load().hqr_lstsq_ir(ctypes.c_void_p(dA), M, N, lda, ctypes.c_void_p(db), ctypes.c_void_p(dx),
+                             ctypes.c_void_p(dr) if dr else None, ctypes.byref(params),
+                             ctypes.byref(exec_) if exec_ is not None else None, max_iter, tol,
+                             ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(stream), ctypes.byref(info))
+    _check("hqr_lstsq_ir", rc)
+    return info
 
 
 def apply_workspace_size(M: int, nrhs: int, params: Params) -> int:

@@ -109,33 +109,17 @@ int get_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, DevicePlan*
   return 0;
 }
 
-// Workspace of hqr_apply_qt/_q/hqr_lstsq: control words, one dependency
-// counter per block of B, and B in blocks of nb x 64.
-struct ApplyLayout {
-  int32_t mt, nbc;
-  size_t ctrl, cnt, blocks, total;
-};
-
-ApplyLayout apply_layout_for(int64_t M, int64_t nrhs, const hqr_params& p) {
-  ApplyLayout L{};
-  L.mt = (int32_t)((M + p.nb - 1) / p.nb);
-  L.nbc = (int32_t)((nrhs + 63) / 64);
-  size_t off = 0;
-  L.ctrl = off; off = align256(off + kCtrlWords * sizeof(int32_t));
-  L.cnt = off; off = align256(off + (size_t)L.mt * L.nbc * sizeof(int32_t));
-  L.blocks = off; off = align256(off + (size_t)L.mt * L.nbc * p.nb * 64 * sizeof(double));
-  L.total = off;
-  return L;
-}
+}  // namespace
 
 // B (M x nrhs) <- Q^T B (trans = 1) or Q B with the factorization held in
 // dwork; B is copied into the blocks of bwork, transformed, and copied back
 // when copy_out.
 int run_apply(int trans, int64_t M, int64_t N, const hqr_params& p, const hqr_exec* exec, const void* dwork,
               size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
-              void* stream, bool copy_out) {
-  const Layout L = layout_for(M, N, p);
-  const ApplyLayout AL = apply_layout_for(M, nrhs, p);
+              void* stream, bool copy_out, bool f32) {
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  const Layout L = layout_for(M, N, p, 0, es);
+  const ApplyLayout AL = apply_layout_for(M, nrhs, p, es);
   if (L.mt > 65535 || L.nt > 65535 || AL.nbc > 65535) return -2;
   if (work_bytes < L.total) return -7;
   if (bwork_bytes < AL.total) return -12;
@@ -162,14 +146,15 @@ int run_apply(int trans, int64_t M, int64_t N, const hqr_params& p, const hqr_ex
   a.chunks = 1;
   a.cnt_cols = AL.nbc;
   a.trans = trans;
-  if ((rc = launch_tile_copy(dB, ldb, a.B, M, nrhs, p.nb, 64, AL.mt, AL.nbc, true, stream))) return rc;
+  if ((rc = launch_tile_copy(dB, 0, ldb, a.B, f32, M, nrhs, p.nb, 64, AL.mt, AL.nbc, true, stream))) return rc;
   const int64_t nwords = (int64_t)((AL.blocks - AL.ctrl) / sizeof(int32_t));  // ctrl + counters
   if ((rc = launch_zero_i32(a.ctrl, nwords, stream))) return rc;
   if (a.ntasks > 0) {
-    int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb);
-    if ((rc = launch_persistent(p.nb, a, workers, stream))) return rc;
+    int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb, f32);
+    if ((rc = launch_persistent(p.nb, a, workers, stream, f32))) return rc;
   }
-  if (copy_out && (rc = launch_tile_copy(dB, ldb, a.B, M, nrhs, p.nb, 64, AL.mt, AL.nbc, false, stream))) return rc;
+  if (copy_out && (rc = launch_tile_copy(dB, 0, ldb, a.B, f32, M, nrhs, p.nb, 64, AL.mt, AL.nbc, false, stream)))
+    return rc;
   return 0;
 }
 
@@ -193,8 +178,7 @@ int check_apply_args(int64_t M, int64_t N, const hqr_params* params, const void*
 // f32: the factorization runs in FP32 on float tiles; a_f32: dA holds
 // float (else double, rounded to float on the way in when f32).
 int run_factor(void* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& p, const hqr_exec& ex, void* dwork,
-               double* dB, int64_t ldb, int32_t nrhs, void* stream, bool copy_a_out, bool f32 = false,
-               bool a_f32 = false) {
+               double* dB, int64_t ldb, int32_t nrhs, void* stream, bool copy_a_out, bool f32, bool a_f32) {
   const size_t es = f32 ? sizeof(float) : sizeof(double);
   const Layout L = layout_for(M, N, p, nrhs, es);
   ColumnChunks cc;
@@ -236,7 +220,6 @@ int run_factor(void* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& p,
   return 0;
 }
 
-}  // namespace
 }  // namespace hqr
 
 using namespace hqr;
@@ -326,7 +309,7 @@ int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* 
   hqr_exec ex{0, 0, 0};
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -6;
-  return run_factor(dA, M, N, lda, *params, ex, dwork, nullptr, 0, 0, stream, true);
+  return run_factor(dA, M, N, lda, *params, ex, dwork, nullptr, 0, 0, stream, true, false, false);
 }
 
 int hqr_workspace_size_f32(int64_t M, int64_t N, const hqr_params* params, size_t* bytes) {
@@ -368,14 +351,14 @@ int hqr_apply_qt(int64_t M, int64_t N, const hqr_params* params, const hqr_exec*
                  size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
                  void* stream) {
   if (int rc = check_apply_args(M, N, params, dwork, dB, ldb, nrhs, bwork)) return rc;
-  return run_apply(1, M, N, *params, exec, dwork, work_bytes, dB, ldb, nrhs, bwork, bwork_bytes, stream, true);
+  return run_apply(1, M, N, *params, exec, dwork, work_bytes, dB, ldb, nrhs, bwork, bwork_bytes, stream, true, false);
 }
 
 int hqr_apply_q(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* exec, const void* dwork,
                 size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
                 void* stream) {
   if (int rc = check_apply_args(M, N, params, dwork, dB, ldb, nrhs, bwork)) return rc;
-  return run_apply(0, M, N, *params, exec, dwork, work_bytes, dB, ldb, nrhs, bwork, bwork_bytes, stream, true);
+  return run_apply(0, M, N, *params, exec, dwork, work_bytes, dB, ldb, nrhs, bwork, bwork_bytes, stream, true, false);
 }
 
 int hqr_lstsq_workspace_size(int64_t M, int64_t N, int32_t nrhs, const hqr_params* params, size_t* bytes) {
@@ -406,7 +389,7 @@ int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t
   hqr_exec ex{0, 0, 0};
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -9;
-  int rc = run_factor(dA, M, N, lda, p, ex, dwork, dB, ldb, nrhs, stream, true);
+  int rc = run_factor(dA, M, N, lda, p, ex, dwork, dB, ldb, nrhs, stream, true, false, false);
   if (rc) return rc;
   char* w = (char*)dwork;
   const double* tiles = (const double*)(w + L.tiles);

@@ -1242,6 +1242,166 @@ __global__ __launch_bounds__(NB) void trsm_batched_kernel(const ProbDesc* descs,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Iterative refinement of least squares (FP64 residuals, FP32 factors).
+
+// f = b - r - A x (r may be null).  A: M x N column-major (lda).  Workgroup
+// of 256 threads = 64 rows x 4 column groups (each group sums every fourth
+// column), partial sums combined in a fixed order.
+__global__ __launch_bounds__(256) void ir_residual_kernel(const double* A, int64_t lda, int64_t M, int64_t N,
+                                                          const double* x, const double* b, const double* r,
+                                                          double* f) {
+  __shared__ double part[4][64];
+  const int lr = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 64 + lr;
+  double s = 0.0;
+  if (row < M)
+    for (int64_t j = cg; j < N; j += 4) s += A[row + j * lda] * x[j];
+  part[cg][lr] = s;
+  __syncthreads();
+  if (cg == 0 && row < M)
+    f[row] = b[row] - (r ? r[row] : 0.0) - ((part[0][lr] + part[1][lr]) + (part[2][lr] + part[3][lr]));
+}
+
+// g = -A^T r (SQ = 0), or g_j = sum_i A_ij^2 (SQ = 1, r unused).
+// Workgroup per 8 columns; 256 threads stride over the rows; a fixed
+// reduction tree per column.
+template <int SQ>
+__global__ __launch_bounds__(256) void ir_atr_kernel(const double* A, int64_t lda, int64_t M, int64_t N,
+                                                     const double* r, double* g) {
+  __shared__ double part[8][257];
+  const int t = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * 8;
+  const int nc = (int)((N - c0) < 8 ? (N - c0) : 8);
+  double s[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s[c] = 0.0;
+  for (int64_t i = t; i < M; i += 256) {
+    const double ri = SQ ? 0.0 : r[i];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (c < nc) {
+        const double aij = A[i + (c0 + c) * lda];
+        s[c] += aij * (SQ ? aij : ri);
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) part[c][t] = s[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) part[c][t] += part[c][t + w];
+    }
+    __syncthreads();
+  }
+  if (t < nc) g[c0 + t] = SQ ? part[t][0] : -part[t][0];
+}
+
+// Triangular solves with the leading N x N triangle R of float tiles (tile
+// (i, j) at (j mt + i) nb^2, column-major inside), in FP64 arithmetic, one
+// workgroup of 256 threads, y overwritten by the solution:
+//   TRANS = 0: R x = y (backward);  TRANS = 1: R^T x = y (forward).
+// Blocks of 64 unknowns: wave 0 solves the block's 64 x 64 triangle lane
+// by lane (lane l holds unknown k0 + l), then all threads remove the block
+// from the remaining right-hand side.
+template <int TRANS>
+__global__ __launch_bounds__(256) void ir_trsv_kernel(const float* R, int nb, int mt, int64_t N, double* y) {
+  __shared__ double xb[64];
+  __shared__ float Rd[64 * 65];  // the block's diagonal triangle: Rd[i * 65 + j] = R(k0 + i, k0 + j)
+  const int t = threadIdx.x, lane = t & 63;
+  const int64_t nblk = (N + 63) / 64;
+  const int64_t tsz = (int64_t)nb * nb;
+  for (int64_t bi = 0; bi < nblk; ++bi) {
+    const int64_t blk = TRANS ? bi : nblk - 1 - bi;
+    const int64_t k0 = blk * 64;
+    const int nv = (int)((N - k0) < 64 ? (N - k0) : 64);
+    // the 64 rows / columns k0.. lie inside tile row / column kt (nb is a multiple of 64)
+    const int64_t kt = k0 / nb, ko = k0 - kt * nb;
+    const float* Rkk = R + (kt * mt + kt) * tsz + ko + ko * nb;  // R(k0, k0)
+    for (int e = t; e < 64 * 64; e += 256) {
+      const int i = e & 63, j = e >> 6;
+      Rd[i * 65 + j] = (i < nv && j < nv && i <= j) ? Rkk[i + (int64_t)j * nb] : 0.0f;
+    }
+    __syncthreads();
+    if (t < 64) {
+      double v = lane < nv ? y[k0 + lane] : 0.0;
+      for (int s = 0; s < nv; ++s) {
+        const int c = TRANS ? s : nv - 1 - s;
+        const double xc = __shfl(v, c) / (double)Rd[c * 65 + c];
+        if (lane == c) v = xc;
+        // TRANS: lanes after c take R(k0+c, k0+lane) x_c; else lanes before c take R(k0+lane, k0+c) x_c
+        if (TRANS ? (lane > c && lane < nv) : (lane < c))
+          v -= (double)(TRANS ? Rd[c * 65 + lane] : Rd[lane * 65 + c]) * xc;
+      }
+      xb[lane] = v;
+      if (lane < nv) y[k0 + lane] = v;
+    }
+    __syncthreads();
+    // the rest of the right-hand side: TRANS rows after the block (R(k0 + c, a),
+    // contiguous in c), else rows before it (R(a, k0 + c), stride nb in c)
+    const int64_t lo = TRANS ? k0 + nv : 0, hi = TRANS ? N : k0;
+    for (int64_t a = lo + t; a < hi; a += 256) {
+      const int64_t at = a / nb, ao = a - at * nb;
+      const float* p = TRANS ? R + (at * mt + kt) * tsz + ko + ao * nb   // R(k0, a)
+                             : R + (kt * mt + at) * tsz + ao + ko * nb;  // R(a, k0)
+      const int64_t step = TRANS ? 1 : nb;
+      double acc0 = 0.0, acc1 = 0.0;
+      int c = 0;
+      for (; c + 1 < nv; c += 2) {
+        acc0 += (double)p[c * step] * xb[c];
+        acc1 += (double)p[(c + 1) * step] * xb[c + 1];
+      }
+      if (c < nv) acc0 += (double)p[c * step] * xb[c];
+      y[a] -= acc0 + acc1;
+    }
+    __syncthreads();
+  }
+}
+
+// y = d(0:N) - h;  then d(0:N) = h  (the two uses of h in one correction).
+__global__ void ir_split_kernel(double* d, const double* h, double* y, int64_t N) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    y[i] = d[i] - h[i];
+    d[i] = h[i];
+  }
+}
+
+// x += dx (N), r += dr (M).
+__global__ void ir_update_kernel(double* x, const double* dx, int64_t N, double* r, const double* dr, int64_t M) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < N) x[i] += dx[i];
+    r[i] += dr[i];
+  }
+}
+
+// out[k] = sum of squares of vector k (v[k], n[k] entries; a null vector
+// gives 0), k < 4; one workgroup, fixed order.
+struct Vec4Args {
+  const double* v[4];
+  int64_t n[4];
+};
+__global__ __launch_bounds__(256) void ir_norms_kernel(Vec4Args a, double* out) {
+  __shared__ double part[4][256];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double sk = 0.0;
+    if (a.v[k])
+      for (int64_t i = t; i < a.n[k]; i += 256) sk += a.v[k][i] * a.v[k][i];
+    part[k][t] = sk;
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) part[k][t] += part[k][t + w];
+    }
+    __syncthreads();
+  }
+  if (t < 4) out[t] = part[t][0];
+}
+
 // Records the last HIP failure for hqr_last_error().
 static thread_local char g_last_error[256];
 
@@ -1258,6 +1418,51 @@ static int grid_for(int64_t n) {
   if (g > 65536) g = 65536;
   if (g < 1) g = 1;
   return (int)g;
+}
+
+int launch_ir_residual(const double* A, int64_t lda, int64_t M, int64_t N, const double* x, const double* b,
+                       const double* r, double* f, void* stream) {
+  hipLaunchKernelGGL(ir_residual_kernel, dim3((unsigned)((M + 63) / 64)), dim3(256), 0, (hipStream_t)stream, A, lda,
+                     M, N, x, b, r, f);
+  return record_hip(hipGetLastError(), "ir_residual_kernel launch");
+}
+
+int launch_ir_atr(const double* A, int64_t lda, int64_t M, int64_t N, const double* r, double* g, void* stream) {
+  if (r)
+    hipLaunchKernelGGL(ir_atr_kernel<0>, dim3((unsigned)((N + 7) / 8)), dim3(256), 0, (hipStream_t)stream, A, lda, M,
+                       N, r, g);
+  else
+    hipLaunchKernelGGL(ir_atr_kernel<1>, dim3((unsigned)((N + 7) / 8)), dim3(256), 0, (hipStream_t)stream, A, lda, M,
+                       N, r, g);
+  return record_hip(hipGetLastError(), "ir_atr_kernel launch");
+}
+
+int launch_ir_trsv(const float* R, int nb, int mt, int64_t N, double* y, bool trans, void* stream) {
+  if (trans)
+    hipLaunchKernelGGL(ir_trsv_kernel<1>, dim3(1), dim3(256), 0, (hipStream_t)stream, R, nb, mt, N, y);
+  else
+    hipLaunchKernelGGL(ir_trsv_kernel<0>, dim3(1), dim3(256), 0, (hipStream_t)stream, R, nb, mt, N, y);
+  return record_hip(hipGetLastError(), "ir_trsv_kernel launch");
+}
+
+int launch_ir_split(double* d, const double* h, double* y, int64_t N, void* stream) {
+  hipLaunchKernelGGL(ir_split_kernel, dim3(grid_for(N)), dim3(256), 0, (hipStream_t)stream, d, h, y, N);
+  return record_hip(hipGetLastError(), "ir_split_kernel launch");
+}
+
+int launch_ir_update(double* x, const double* dx, int64_t N, double* r, const double* dr, int64_t M, void* stream) {
+  hipLaunchKernelGGL(ir_update_kernel, dim3(grid_for(M)), dim3(256), 0, (hipStream_t)stream, x, dx, N, r, dr, M);
+  return record_hip(hipGetLastError(), "ir_update_kernel launch");
+}
+
+int launch_ir_norms(const double* const* v, const int64_t* n, double* out, void* stream) {
+  Vec4Args a;
+  for (int k = 0; k < 4; ++k) {
+    a.v[k] = v[k];
+    a.n[k] = n[k];
+  }
+  hipLaunchKernelGGL(ir_norms_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, a, out);
+  return record_hip(hipGetLastError(), "ir_norms_kernel launch");
 }
 
 int launch_zero_i32(int32_t* p, int64_t n, void* stream) {

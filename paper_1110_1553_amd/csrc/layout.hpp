@@ -48,4 +48,34 @@ inline Layout layout_for(int64_t M, int64_t N, const hqr_params& p, int64_t nrhs
   return L;
 }
 
+// Workspace of hqr_apply_qt/_q/hqr_lstsq: control words, one dependency
+// counter per block of B, and B in blocks of nb x 64.
+struct ApplyLayout {
+  int32_t mt, nbc;
+  size_t ctrl, cnt, blocks, total;
+};
+
+inline ApplyLayout apply_layout_for(int64_t M, int64_t nrhs, const hqr_params& p, size_t esize = sizeof(double)) {
+  ApplyLayout L{};
+  L.mt = (int32_t)((M + p.nb - 1) / p.nb);
+  L.nbc = (int32_t)((nrhs + 63) / 64);
+  size_t off = 0;
+  L.ctrl = off; off = align256(off + kCtrlWords * sizeof(int32_t));
+  L.cnt = off; off = align256(off + (size_t)L.mt * L.nbc * sizeof(int32_t));
+  L.blocks = off; off = align256(off + (size_t)L.mt * L.nbc * p.nb * 64 * esize);
+  L.total = off;
+  return L;
+}
+
+// Library-internal launch sequences (api.cpp).  run_factor: copies A (and
+// nrhs right-hand sides) into the workspace tiles, runs the factorization
+// (f32: FP32 tiles and kernels; a_f32: A holds float), copies A back when
+// copy_a_out.  run_apply: B <- Q^T B (trans) or Q B with the factorization
+// in dwork (f32: FP32 factors and B blocks; B itself stays double).
+int run_factor(void* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& p, const hqr_exec& ex, void* dwork,
+               double* dB, int64_t ldb, int32_t nrhs, void* stream, bool copy_a_out, bool f32, bool a_f32);
+int run_apply(int trans, int64_t M, int64_t N, const hqr_params& p, const hqr_exec* exec, const void* dwork,
+              size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
+              void* stream, bool copy_out, bool f32);
+
 }  // namespace hqr

@@ -1,0 +1,183 @@
+// Mixed-precision least squares: FP32 tiled QR of A, then iterative
+// refinement of the augmented system
+//     [ I   A ] [ r ]   [ b ]
+//     [ A^T 0 ] [ x ] = [ 0 ]
+// (Bjorck's refinement for least squares) with the residuals of both block
+// rows in FP64 and each correction solved with the FP32 factors
+// (entry point hqr_lstsq_ir of include/hqr.h).
+//
+// With A = Q [R; 0], the correction of the residuals f = b - r - A x and
+// g = -A^T r is
+//     h = R^{-T} g,   d = Q^T f,   dx = R^{-1} (d(0:N) - h),   dr = Q [h; d(N:M)]
+// and x += dx, r += dr.  Starting from x = 0, r = 0 the first correction is
+// the plain FP32 least-squares solution.  The iterate is judged by the
+// normwise backward error of the augmented system,
+//     eta = sqrt(||f||^2 + ||g||^2) / (||A||_F (||x|| + ||r||) + ||b||),
+// evaluated before each correction; the loop stops once eta <= tol, when a
+// correction did not lower eta (the attainable accuracy is reached), or
+// after max_iter corrections.
+//
+// Workspace: the FP32 factorization (tiles and T factors), the FP32 block of
+// the Q applications, then the FP64 vectors x (N), r (M), f (M), g (N),
+// y (N) and four words for the norms.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/hqr.h"
+#include "elim.hpp"
+#include "layout.hpp"
+#include "task.hpp"
+
+namespace hqr {
+namespace {
+
+struct IrLayout {
+  Layout fac;
+  ApplyLayout app;
+  size_t app_off, x, r, f, g, y, norms, total;
+};
+
+IrLayout ir_layout(int64_t M, int64_t N, const hqr_params& p) {
+  IrLayout L{};
+  L.fac = layout_for(M, N, p, 0, sizeof(float));
+  L.app = apply_layout_for(M, 1, p, sizeof(float));
+  size_t off = L.fac.total;
+  L.app_off = off; off = align256(off + L.app.total);
+  L.x = off; off = align256(off + (size_t)N * sizeof(double));
+  L.r = off; off = align256(off + (size_t)M * sizeof(double));
+  L.f = off; off = align256(off + (size_t)M * sizeof(double));
+  L.g = off; off = align256(off + (size_t)N * sizeof(double));
+  L.y = off; off = align256(off + (size_t)N * sizeof(double));
+  L.norms = off; off = align256(off + 4 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+}  // namespace hqr
+
+using namespace hqr;
+
+extern "C" {
+
+int hqr_lstsq_ir_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* bytes) {
+  if (M < 1 || M < N) return -1;
+  if (N < 1) return -2;
+  if (!params || check_params(*params)) return -3;
+  if (!bytes) return -4;
+  *bytes = ir_layout(M, N, *params).total;
+  return 0;
+}
+
+int hqr_lstsq_ir(const double* dA, int64_t M, int64_t N, int64_t lda, const double* db, double* dx, double* dr,
+                 const hqr_params* params, const hqr_exec* exec, int32_t max_iter, double tol, void* dwork,
+                 size_t work_bytes, void* stream, hqr_ir_info* info) {
+  if (!dA) return -1;
+  if (M < 1 || M < N) return -2;
+  if (N < 1) return -3;
+  if (lda < M) return -4;
+  if (!db) return -5;
+  if (!dx) return -6;
+  if (!params || check_params(*params)) return -8;
+  hqr_exec ex{0, 0, 0};
+  if (exec) ex = *exec;
+  if (ex.order != 0 && ex.order != 1) return -9;
+  if (max_iter < 1) return -10;
+  if (!(tol >= 0.0)) return -11;
+  if (!dwork) return -12;
+  const hqr_params& p = *params;
+  const IrLayout L = ir_layout(M, N, p);
+  if (L.fac.mt > 65535 || L.fac.nt > 65535) return -2;
+  if (work_bytes < L.total) return -13;
+  if (info) std::memset(info, 0, sizeof(*info));
+  char* w = (char*)dwork;
+  double* x = (double*)(w + L.x);
+  double* r = (double*)(w + L.r);
+  double* f = (double*)(w + L.f);
+  double* g = (double*)(w + L.g);
+  double* y = (double*)(w + L.y);
+  double* norms = (double*)(w + L.norms);
+  double* colsq = y;  // squared column norms of A, before y is needed
+  const float* Rt = (const float*)(w + L.fac.tiles);
+  void* bwork = w + L.app_off;
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  // FP32 factorization of A (A itself is left untouched: copied and rounded into the tiles)
+  if ((rc = run_factor(const_cast<double*>(dA), M, N, lda, p, ex, dwork, nullptr, 0, 0, stream, false, true, false)))
+    return rc;
+  // x = 0, r = 0
+  if ((rc = launch_zero_i32((int32_t*)x, (int64_t)((L.f - L.x) / sizeof(int32_t)), stream))) return rc;
+  // ||A||_F and ||b||, once
+  auto read_norms = [&](double* host) -> int {
+    if (int e = record_hip(hipMemcpyAsync(host, norms, 4 * sizeof(double), hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync(ir norms)"))
+      return e;
+    return record_hip(hipStreamSynchronize(s), "hipStreamSynchronize(ir)");
+  };
+  if ((rc = launch_ir_atr(dA, lda, M, N, nullptr, colsq, stream))) return rc;
+  {
+    const double* v[4] = {colsq, db, nullptr, nullptr};
+    const int64_t n[4] = {N, M, 0, 0};
+    if ((rc = launch_ir_norms(v, n, norms, stream))) return rc;
+  }
+  double nrm[4];
+  if ((rc = read_norms(nrm))) return rc;
+  const double normA = std::sqrt(nrm[0]), normb = std::sqrt(nrm[1]);
+  int it = 0;
+  double eta = INFINITY, prev = INFINITY;
+  bool converged = false;
+  for (;;) {
+    if ((rc = launch_ir_residual(dA, lda, M, N, x, db, r, f, stream))) return rc;       // f = b - r - A x
+    if ((rc = launch_ir_atr(dA, lda, M, N, r, g, stream))) return rc;                   // g = -A^T r
+    {
+      const double* v[4] = {f, g, x, r};
+      const int64_t n[4] = {M, N, N, M};
+      if ((rc = launch_ir_norms(v, n, norms, stream))) return rc;
+    }
+    if ((rc = read_norms(nrm))) return rc;
+    const double den = normA * (std::sqrt(nrm[2]) + std::sqrt(nrm[3])) + normb;
+    eta = den > 0.0 ? std::sqrt(nrm[0] + nrm[1]) / den : 0.0;
+    if (info && it < 32) info->history[it] = eta;
+    if (eta <= tol) {
+      converged = true;
+      break;
+    }
+    if (it >= max_iter || !std::isfinite(eta) || eta >= prev) break;
+    prev = eta;
+    if ((rc = launch_ir_trsv(Rt, p.nb, L.fac.mt, N, g, true, stream))) return rc;       // h = R^{-T} g
+    if ((rc = run_apply(1, M, N, p, &ex, dwork, work_bytes, f, M, 1, bwork, L.app.total, stream, true, true)))
+      return rc;                                                                         // f = Q^T f
+    if ((rc = launch_ir_split(f, g, y, N, stream))) return rc;                          // y = d1 - h, d1 = h
+    if ((rc = launch_ir_trsv(Rt, p.nb, L.fac.mt, N, y, false, stream))) return rc;      // dx = R^{-1} y
+    if ((rc = run_apply(0, M, N, p, &ex, dwork, work_bytes, f, M, 1, bwork, L.app.total, stream, true, true)))
+      return rc;                                                                         // dr = Q [h; d2]
+    if ((rc = launch_ir_update(x, y, N, r, f, M, stream))) return rc;                    // x += dx, r += dr
+    ++it;
+  }
+  // the launches record a watchdog abort in their control words
+  int32_t st[2] = {0, 0};
+  if ((rc = record_hip(hipMemcpyAsync(&st[0], w + L.fac.ctrl + sizeof(int32_t), sizeof(int32_t),
+                                      hipMemcpyDeviceToHost, s), "hipMemcpyAsync(ir status)")))
+    return rc;
+  if ((rc = record_hip(hipMemcpyAsync(&st[1], w + L.app_off + L.app.ctrl + sizeof(int32_t), sizeof(int32_t),
+                                      hipMemcpyDeviceToHost, s), "hipMemcpyAsync(ir status)")))
+    return rc;
+  if ((rc = record_hip(hipMemcpyAsync(dx, x, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s),
+                       "hipMemcpyAsync(x)")))
+    return rc;
+  if (dr && (rc = record_hip(hipMemcpyAsync(dr, r, (size_t)M * sizeof(double), hipMemcpyDeviceToDevice, s),
+                             "hipMemcpyAsync(r)")))
+    return rc;
+  if ((rc = record_hip(hipStreamSynchronize(s), "hipStreamSynchronize(ir)"))) return rc;
+  if (info) {
+    info->iterations = it;
+    info->converged = converged ? 1 : 0;
+    info->eta = eta;
+  }
+  if (st[0] || st[1]) return st[0] ? st[0] : st[1];
+  return 0;
+}
+
+}  // extern "C"

@@ -97,6 +97,19 @@ int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, 
 int launch_trsm_batched(int nb, const ProbDesc* d, char* w, int32_t* ctrl, int32_t* info, int count, int gmax,
                         void* stream);
 
+// Least-squares refinement steps (FP64 vectors; R as float tiles of nb,
+// mt tile rows): f = b - r - A x (r may be null); g = -A^T r (r null: g_j =
+// squared norm of column j); y <- R^{-1} y or R^{-T} y; y = d(0:N) - h
+// then d(0:N) = h; x += dx, r += dr; out[k] = ||v[k]||^2 (n[k] entries,
+// k < 4).
+int launch_ir_residual(const double* A, int64_t lda, int64_t M, int64_t N, const double* x, const double* b,
+                       const double* r, double* f, void* stream);
+int launch_ir_atr(const double* A, int64_t lda, int64_t M, int64_t N, const double* r, double* g, void* stream);
+int launch_ir_trsv(const float* R, int nb, int mt, int64_t N, double* y, bool trans, void* stream);
+int launch_ir_split(double* d, const double* h, double* y, int64_t N, void* stream);
+int launch_ir_update(double* x, const double* dx, int64_t N, double* r, const double* dr, int64_t M, void* stream);
+int launch_ir_norms(const double* const* v, const int64_t* n, double* out, void* stream);
+
 // Workgroups that fit on the device at once (per CU occupancy x CUs).
 int default_workers(int nb, bool f32 = false);
 
