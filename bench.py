@@ -35,12 +35,12 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix
 
-# HBM bytes per launch of persistent_kernel<256> from two rocprofv3 --pmc runs
+# HBM bytes per launch of persistent_kernel<double, 256> from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE), each scaled by what the counter reads for the
 # copy-in kernel of known size.  Valid only for the kernel source they were
 # measured on (first 16 hex digits of the SHA-256 of csrc/kernels.hip).
 TRAFFIC = {
-    "tall-hqr": {"kernels_sha256": "9ccd2e7c360edbfe", "read": 46.17e9, "write": 49.56e9,
+    "tall-hqr": {"kernels_sha256": "bbed648c8f54c8ce", "read": 46.24e9, "write": 49.56e9,
                  "profile": "profiles/persistent_kernel_tall-hqr.md"},
 }
 
