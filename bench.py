@@ -17,8 +17,9 @@ Next to the headline line it measures (keys "lstsq" and "serving"):
 * continuous-batching serving of 4096 least-squares requests (rows uniform
   in [256, 16384], columns uniform in [32, 512], one right-hand side,
   Poisson arrivals at 0.8 of the measured saturated throughput, 8 GiB
-  workspace budget, tile size and tree autotuned on the first 64 requests):
-  solves per second and p50/p99 latency.
+  workspace budget in two slots with a stream each, factors of served
+  requests kept on the device within 32 GiB, tile size and tree autotuned
+  on the first 64 requests): solves per second and p50/p99 latency.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 Prints one JSON line.
@@ -240,7 +241,7 @@ def run_serving(device, count=4096, budget_gib=8, seed=5, load=0.8, tune_sample=
         torch.cuda.synchronize(device)
         return reqs
 
-    be = serve.GpuBackend(params, budget_gib << 30, max_inflight=2, device=device)
+    be = serve.GpuBackend(params, budget_gib << 30, max_inflight=2, device=device, factor_budget=32 << 30)
     # saturated throughput: every request waiting at the start
     reqs = make_requests(np.zeros(count))
     sch = serve.Scheduler(be)
@@ -248,6 +249,7 @@ def run_serving(device, count=4096, budget_gib=8, seed=5, load=0.8, tune_sample=
     span = max(r.done for r in reqs)
     sat = count / span
     del reqs, sch
+    be.store = serve.FactorStore(32 << 30)  # the second run starts with no resident factors
     # Poisson arrivals at `load` times that rate
     arrivals = np.cumsum(inputs.arrival_gaps(count, load * sat, seed + 1))
     reqs = make_requests(arrivals)
@@ -260,7 +262,11 @@ def run_serving(device, count=4096, budget_gib=8, seed=5, load=0.8, tune_sample=
            "params": best, "budget_GiB": budget_gib, "saturated_solves_per_s": sat,
            "saturated_gflops": flops / span / 1e9, "arrival_rate_per_s": load * sat,
            "solves_per_s": s["solves_per_s"], "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"],
-           "batches": len(sch.batches), "mean_batch": count / len(sch.batches), "failed": bad}
+           "batches": len(sch.batches), "mean_batch": count / len(sch.batches), "failed": bad,
+           "batches_launched_while_another_ran": sum(1 for i in range(1, len(sch.batches))
+                                                     if sch.batches[i]["t_launch"] < sch.batches[i - 1]["t_done"]),
+           "resident_factorizations": len(be.store.items), "resident_GiB": be.store.used / 2 ** 30,
+           "evicted": be.store.evicted}
     del reqs, sch, be
     torch.cuda.empty_cache()
     return out

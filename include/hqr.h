@@ -369,6 +369,16 @@ int hqr_batch_run(const hqr_batch* b, void* dwork, size_t work_bytes, void* stre
 int hqr_batch_status(const hqr_batch* b, const void* dwork, void* stream, double timeout_s, int32_t* status,
                      int32_t* first_zero);
 
+/* Copies the factorization of problem q (its T factors and the tiles of its
+ * matrix) out of the batch workspace into dst, a workspace of
+ * hqr_workspace_size(M[q], N[q]) bytes laid out as hqr_factor leaves it,
+ * so that the factors stay on the device after the batch workspace is
+ * reused (hqr_apply_qt / hqr_apply_q / hqr_solve take dst).  Enqueued on
+ * `stream` after the batch.  Errors: -1 b NULL, -2 q out of range, -3 dwork
+ * NULL, -4 dst NULL, -5 dst_bytes too small. */
+int hqr_batch_export_factors(const hqr_batch* b, int32_t q, const void* dwork, void* dst, size_t dst_bytes,
+                             void* stream);
+
 /* Frees the host batch object (the caller's device buffers are untouched). */
 void hqr_batch_destroy(hqr_batch* b);
 
@@ -385,6 +395,16 @@ int hqr_lstsq_batched(int32_t count, double* const* dA, const int64_t* M, const 
  * -6 bytes NULL. */
 int hqr_lstsq_batched_workspace_size(int32_t count, const int64_t* M, const int64_t* N, const int32_t* nrhs,
                                      const hqr_params* params, size_t* bytes);
+
+/* Least squares with a finished factorization: B (M x nrhs) <- Q^T B, then
+ * x = R^{-1} (Q^T B)(0:N) in rows 0..N-1 of B (rows N..M-1 keep the
+ * residual components), with the factorization of hqr_factor (or one
+ * exported by hqr_batch_export_factors) in dwork and bwork as for
+ * hqr_apply_qt.  A zero diagonal entry of R is reported by hqr_status(bwork)
+ * as HQR_ERR_SINGULAR.  Errors as hqr_apply_qt. */
+int hqr_solve(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* exec, const void* dwork,
+              size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
+              void* stream);
 
 /* Status word of the last launch that used the workspace `dwork` (a
  * factorization or least-squares workspace, or the bwork of hqr_apply_qt/_q):

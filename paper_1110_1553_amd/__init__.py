@@ -24,7 +24,7 @@ from ._lib import (BINARY, CHAIN, FIBONACCI, FLAT, GREEDY, OPS, Exec, HQRError, 
 __all__ = ["FLAT", "BINARY", "GREEDY", "FIBONACCI", "CHAIN", "OPS", "Params", "Exec", "HQRError", "make_params",
            "make_exec", "elimlist", "validate", "dag_stats", "workspace_size", "apply_workspace_size",
            "lstsq_workspace_size", "factor",
-           "apply_qt", "apply_q", "lstsq", "lstsq_ir", "lstsq_batched", "BatchedLstsq", "colmajor", "r_of", "Workspace", "ApplyWorkspace", "status",
+           "apply_qt", "apply_q", "solve", "lstsq", "lstsq_ir", "lstsq_batched", "BatchedLstsq", "colmajor", "r_of", "Workspace", "ApplyWorkspace", "status",
            "release_plans", "version"]
 
 
@@ -138,6 +138,25 @@ def apply_qt(B, M, N, params, work, exec_=None, bwork=None, stream=None, check=T
 def apply_q(B, M, N, params, work, exec_=None, bwork=None, stream=None, check=True):
     """B <- Q B in place; see :func:`apply_qt`."""
     return _apply(False, B, M, N, params, work, exec_, bwork, stream, check)
+
+
+def solve(B, M, N, params, work, exec_=None, bwork=None, stream=None, check=True):
+    """Least squares with the finished factorization of an M x N matrix held
+    in ``work``: B (column-major M x nrhs) is overwritten by x in its first N
+    rows and the residual components of Q^T B below (hqr_solve)."""
+    import torch
+
+    MB, nrhs, ldb = _colmajor_args(B, "B")
+    if MB != M:
+        raise ValueError("B must have M = %d rows" % M)
+    if bwork is None:
+        bwork = ApplyWorkspace(M, nrhs, params, device=B.device)
+    s = stream if stream is not None else torch.cuda.current_stream(B.device)
+    _lib.solve_ptr(M, N, params, exec_, work.ptr, work.bytes, B.data_ptr(), ldb, nrhs, bwork.ptr, bwork.bytes,
+                   s.cuda_stream)
+    if check:
+        _device_status(bwork, s, "hqr_solve")
+    return bwork
 
 
 def lstsq(A, B, params, exec_=None, work=None, stream=None, check=True):

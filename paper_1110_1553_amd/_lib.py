@@ -51,7 +51,8 @@ EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_s
            "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size", "hqr_lstsq",
            "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_timeline", "hqr_version",
            "hqr_batch_create", "hqr_batch_workspace_size", "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run",
-           "hqr_batch_status", "hqr_batch_destroy", "hqr_lstsq_batched", "hqr_lstsq_batched_workspace_size")
+           "hqr_batch_status", "hqr_batch_destroy", "hqr_lstsq_batched", "hqr_lstsq_batched_workspace_size",
+           "hqr_solve", "hqr_batch_export_factors")
 
 _lib = None
 
@@ -86,6 +87,8 @@ def load():
                                  ctypes.c_size_t, vp, P(IrInfo)]
     apply_args = [i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp, i64, i32, vp, ctypes.c_size_t, vp]
     lib.hqr_apply_qt.argtypes = apply_args
+    lib.hqr_solve.argtypes = apply_args
+    lib.hqr_batch_export_factors.argtypes = [vp, i32, vp, vp, ctypes.c_size_t, vp]
     lib.hqr_apply_q.argtypes = apply_args
     lib.hqr_lstsq_workspace_size.argtypes = [i64, i64, i32, P(Params), P(ctypes.c_size_t)]
     lib.hqr_lstsq.argtypes = [vp, i64, i64, i64, vp, i64, i32, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
@@ -116,7 +119,7 @@ def load():
                  "hqr_lstsq", "hqr_status", "hqr_status_ex", "hqr_workspace_size_f32", "hqr_factor_f32",
                  "hqr_lstsq_ir_workspace_size", "hqr_lstsq_ir", "hqr_batch_create", "hqr_batch_workspace_size",
                  "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run", "hqr_batch_status", "hqr_lstsq_batched",
-                 "hqr_lstsq_batched_workspace_size"):
+                 "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -240,6 +243,14 @@ def apply_ptr(trans: bool, M: int, N: int, params: Params, exec_: Exec, dwork: i
     _check("hqr_apply_qt" if trans else "hqr_apply_q", rc)
 
 
+def solve_ptr(M: int, N: int, params: Params, exec_: Exec, dwork: int, work_bytes: int, dB: int, ldb: int,
+              nrhs: int, bwork: int, bwork_bytes: int, stream: int) -> None:
+    rc = load().hqr_solve(M, N, ctypes.byref(params), ctypes.byref(exec_) if exec_ is not None else None,
+                          ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(dB), ldb, nrhs, ctypes.c_void_p(bwork),
+                          bwork_bytes, ctypes.c_void_p(stream))
+    _check("hqr_solve", rc)
+
+
 def lstsq_workspace_size(M: int, N: int, nrhs: int, params: Params) -> int:
     n = ctypes.c_size_t()
     _check("hqr_lstsq_workspace_size",
@@ -340,6 +351,10 @@ class Batch:
                                                            ctypes.c_void_p(stream), timeout_s, ctypes.byref(s),
                                                            _ptr(fz)))
         return s.value, fz
+
+    def export_factors(self, q: int, dwork: int, dst: int, dst_bytes: int, stream: int) -> None:
+        _check("hqr_batch_export_factors", load().hqr_batch_export_factors(
+            self.handle, q, ctypes.c_void_p(dwork), ctypes.c_void_p(dst), dst_bytes, ctypes.c_void_p(stream)))
 
     def close(self) -> None:
         if self.handle:

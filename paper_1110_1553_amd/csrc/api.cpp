@@ -402,6 +402,25 @@ int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t
   return launch_tile_copy(dB, ldb, Bt, M, nrhs, p.nb, p.nb, L.mt, L.nrt, false, stream);
 }
 
+int hqr_solve(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* exec, const void* dwork,
+              size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
+              void* stream) {
+  if (int rc = check_apply_args(M, N, params, dwork, dB, ldb, nrhs, bwork)) return rc;
+  const hqr_params& p = *params;
+  // B <- Q^T B, left in bwork's blocks of nb x 64
+  int rc = run_apply(1, M, N, p, exec, dwork, work_bytes, dB, ldb, nrhs, bwork, bwork_bytes, stream, false, false);
+  if (rc) return rc;
+  const Layout L = layout_for(M, N, p);
+  const ApplyLayout AL = apply_layout_for(M, nrhs, p);
+  char* bw = (char*)bwork;
+  double* Bb = (double*)(bw + AL.blocks);
+  const double* tiles = (const double*)((const char*)dwork + L.tiles);
+  const int groups = AL.nbc > 1 ? 4 : (nrhs + 15) / 16;
+  if ((rc = launch_trsm(p.nb, tiles, Bb, 1, (int32_t*)(bw + AL.ctrl), N, L.mt, L.nt, AL.nbc, groups, stream)))
+    return rc;
+  return launch_tile_copy(dB, ldb, Bb, M, nrhs, p.nb, 64, AL.mt, AL.nbc, false, stream);
+}
+
 int hqr_status(const void* dwork, void* stream, int32_t* status) {
   return hqr_status_ex(dwork, stream, 0.0, status, nullptr);
 }

@@ -354,6 +354,30 @@ int hqr_batch_status(const hqr_batch* b, const void* dwork, void* stream, double
   return 0;
 }
 
+int hqr_batch_export_factors(const hqr_batch* b, int32_t q, const void* dwork, void* dst, size_t dst_bytes,
+                             void* stream) {
+  if (!b) return -1;
+  if (q < 0 || q >= b->count) return -2;
+  if (!dwork) return -3;
+  if (!dst) return -4;
+  const Layout L = layout_for(b->M[q], b->N[q], b->p);
+  if (dst_bytes < L.total) return -5;
+  const ProbDesc& d = b->desc[q];
+  const char* w = (const char*)dwork;
+  char* o = (char*)dst;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t tsz = (size_t)L.mt * L.nt * b->p.nb * 16 * sizeof(double);
+  const size_t asz = (size_t)L.mt * L.nt * b->p.nb * b->p.nb * sizeof(double);
+  // control words and counters of the copy start at zero (a status read finds no error)
+  if (int rc = launch_zero_i32((int32_t*)o, (int64_t)(L.tg / sizeof(int32_t)), stream)) return rc;
+  if (int rc = record_hip(hipMemcpyAsync(o + L.tg, w + d.tg, tsz, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(Tg)"))
+    return rc;
+  if (int rc = record_hip(hipMemcpyAsync(o + L.tk, w + d.tk, tsz, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(Tk)"))
+    return rc;
+  return record_hip(hipMemcpyAsync(o + L.tiles, w + d.tiles, asz, hipMemcpyDeviceToDevice, s),
+                    "hipMemcpyAsync(tiles)");
+}
+
 void hqr_batch_destroy(hqr_batch* b) { delete b; }
 
 int hqr_lstsq_batched_workspace_size(int32_t count, const int64_t* M, const int64_t* N, const int32_t* nrhs,

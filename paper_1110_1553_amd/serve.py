@@ -7,10 +7,18 @@ scheduler admits requests from the head of the queue while the batch
 workspace still fits in one slot of the HBM budget (the budget is split into
 ``max_inflight`` workspace slots, allocated once), plans the batch on the
 host and launches it as one batched launch (copy-in, one persistent launch
-over the union of the task graphs, back substitution, copy-out).  Batches
-run in order on one stream, so a batch admitted while another runs starts
-the moment the GPU is free.  A request completes with the end event of its
-batch; its latency is that time minus its arrival time.
+over the union of the task graphs, back substitution, copy-out).  Each
+workspace slot has its own stream: a batch admitted while another runs is
+launched at once, and its persistent workgroups take the compute units that
+the running batch releases as its task list drains, so the two overlap on
+the device.  A request completes with the end event of its batch; its
+latency is that time minus its arrival time.
+
+With a factor budget, the factorization of every served request (its T
+factors and factored tiles) is copied out of the batch workspace into a
+workspace of its own and kept on the device, least recently used first out
+when the budget is full, so that later right-hand sides for the same matrix
+are solved without factoring again (``GpuBackend.solve_resident``).
 
 A request's results do not depend on the batch it was served in: each
 problem of a batched launch runs the same tasks in the same per-tile order
@@ -27,21 +35,51 @@ import numpy as np
 from . import _lib
 
 
-class GpuBackend:
-    """Launches batches through hqr_batch_* on one stream, with workspace
-    slots carved out of one preallocated device buffer."""
+class FactorStore:
+    """Device-resident factorizations under a byte budget, least recently
+    used evicted first."""
 
-    def __init__(self, params, budget_bytes, max_inflight=2, device="cuda", exec_=None, stream=None):
+    def __init__(self, budget_bytes):
+        self.budget = int(budget_bytes)
+        self.used = 0
+        self.items = collections.OrderedDict()  # rid -> (bytes, object)
+        self.evicted = 0
+
+    def put(self, rid, nbytes, obj):
+        if nbytes > self.budget:
+            return False
+        while self.used + nbytes > self.budget and self.items:
+            _, (b, _) = self.items.popitem(last=False)
+            self.used -= b
+            self.evicted += 1
+        self.items[rid] = (nbytes, obj)
+        self.used += nbytes
+        return True
+
+    def get(self, rid):
+        if rid not in self.items:
+            return None
+        self.items.move_to_end(rid)
+        return self.items[rid][1]
+
+
+class GpuBackend:
+    """Launches batches through hqr_batch_*, one stream per workspace slot,
+    with the slots carved out of one preallocated device buffer."""
+
+    def __init__(self, params, budget_bytes, max_inflight=2, device="cuda", exec_=None, factor_budget=0):
         import torch
 
         self.params = params
         self.exec_ = exec_ if exec_ is not None else _lib.make_exec()
         self.device = torch.device(device)
-        # both streams are created by torch (non-blocking with respect to the
-        # null stream): the status of a finished batch is read on `side`
-        # while the next batch still runs on `stream`
-        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        # every stream is created by torch at the default priority and is
+        # non-blocking with respect to the null stream: a finished batch's
+        # status is read on `side` while other batches still run
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(max_inflight)]
+        self.stream = self.streams[0]
         self.side = torch.cuda.Stream(self.device)
+        self.store = FactorStore(factor_budget) if factor_budget > 0 else None
         self.slots = max_inflight
         self.slot_bytes = (int(budget_bytes) // max_inflight) & ~255
         self.pool = torch.empty(self.slot_bytes * max_inflight, dtype=torch.uint8, device=self.device)
@@ -93,14 +131,24 @@ class GpuBackend:
             batch.close()
             return None
         slot = self.free.pop(0)
+        st = self.streams[slot]
         base = self.pool.data_ptr() + slot * self.slot_bytes
         batch.bind([r.A.data_ptr() for r in reqs], [max(r.A.stride(1), r.A.shape[0]) for r in reqs],
                    [r.B.data_ptr() for r in reqs], [max(r.B.stride(1), r.B.shape[0]) for r in reqs],
-                   base, self.slot_bytes, self.stream.cuda_stream)
-        batch.run(base, self.slot_bytes, self.stream.cuda_stream)
+                   base, self.slot_bytes, st.cuda_stream)
+        batch.run(base, self.slot_bytes, st.cuda_stream)
+        kept = []
+        if self.store is not None:
+            from . import Workspace
+
+            with torch.cuda.stream(st):
+                for q, r in enumerate(reqs):
+                    w = Workspace(r.M, r.N, self.params, device=self.device)
+                    batch.export_factors(q, base, w.ptr, w.bytes, st.cuda_stream)
+                    kept.append((r, w))
         end = torch.cuda.Event(enable_timing=True)
-        end.record(self.stream)
-        return {"batch": batch, "slot": slot, "base": base, "end": end}
+        end.record(st)
+        return {"batch": batch, "slot": slot, "base": base, "end": end, "kept": kept}
 
     def done(self, h):
         """Completion time (seconds since start_clock) or None if running."""
@@ -112,7 +160,21 @@ class GpuBackend:
         h["status"], h["first_zero"] = st, first_zero
         h["batch"].close()
         self.free.append(h["slot"])
+        for r, w in h.get("kept", []):
+            self.store.put(r.rid, w.bytes, w)
         return t
+
+    def solve_resident(self, rid, M, N, B):
+        """Least squares for new right-hand sides B (M x nrhs, column-major,
+        overwritten as hqr_solve does) with the kept factorization of
+        request rid; returns False if it was evicted."""
+        from . import solve
+
+        w = self.store.get(rid) if self.store is not None else None
+        if w is None:
+            return False
+        solve(B, M, N, self.params, w, self.exec_, stream=self.side)
+        return True
 
 
 class Request:

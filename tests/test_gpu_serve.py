@@ -55,3 +55,43 @@ def test_served_results_equal_lone_solves(cuda):
         e = np.linalg.norm(X - Xref) / np.linalg.norm(Xref)
         say("  request %d %dx%d: x error %.2e" % (q, m[q], n[q], e))
         assert e <= 1e-11
+
+
+def test_overlap_and_resident_factors(cuda):
+    """Batches admitted while another one runs (two slots, two streams), and
+    factors kept on the device: a second right-hand side for a served
+    request is solved with its resident factorization (hqr_solve)."""
+    import torch
+
+    import paper_1110_1553_amd as h
+    from paper_1110_1553_amd import serve
+
+    n_req = 40
+    m, n = inputs.request_shapes(n_req, 11, mlo=200, mhi=3000, nlo=16, nhi=200)
+    arrivals = np.cumsum(inputs.arrival_gaps(n_req, 20000.0, 12))
+    params = h.make_params(nb=64, low="greedy")
+    As = [inputs.gaussian(int(a), int(b), 1100 + q) for q, (a, b) in enumerate(zip(m, n))]
+    Bs = [inputs.gaussian(int(a), 1, 1200 + q) for q, a in enumerate(m)]
+    dev = lambda X: h.colmajor(torch.from_numpy(np.ascontiguousarray(X)).cuda())  # noqa: E731
+    reqs = [serve.Request(q, dev(As[q]), dev(Bs[q]), float(arrivals[q])) for q in range(n_req)]
+    be = serve.GpuBackend(params, 48 << 20, max_inflight=2, exec_=h.make_exec(spin_limit=4000000),
+                          factor_budget=1 << 30)
+    sch = serve.Scheduler(be)
+    lat = sch.run(reqs)
+    torch.cuda.synchronize()
+    b = sch.batches
+    overlaps = sum(1 for i in range(1, len(b)) if b[i]["t_launch"] < b[i - 1]["t_done"])
+    say("batches %d, launched while the previous one ran: %d, p50 %.2f ms" % (len(b), overlaps,
+                                                                               np.percentile(lat, 50) * 1e3))
+    assert len(b) > 1 and overlaps >= 1
+    assert all(r.status == 0 for r in reqs)
+    for q in (0, n_req // 2, n_req - 1):
+        B2 = inputs.gaussian(int(m[q]), 2, 1300 + q)
+        dB2 = dev(B2)
+        assert be.solve_resident(q, int(m[q]), int(n[q]), dB2)
+        torch.cuda.synchronize()
+        X = dB2.cpu().numpy()[: n[q]]
+        Xref = oq.lstsq(As[q], B2)
+        e = np.linalg.norm(X - Xref) / np.linalg.norm(Xref)
+        say("  request %d %dx%d: second right-hand side from resident factors, x error %.2e" % (q, m[q], n[q], e))
+        assert e <= 1e-11

@@ -118,3 +118,16 @@ def test_max_batch_limits_batch_size():
     be = SimBackend(slot_bytes=1 << 30, slots=1)
     serve.Scheduler(be, max_batch=7).run(reqs)
     assert max(len(b) for b in be.launched) == 7
+
+
+def test_factor_store_keeps_the_most_recent_within_budget():
+    st = serve.FactorStore(100)
+    for rid in range(6):
+        assert st.put(rid, 30, "f%d" % rid)
+    # 3 fit: 3, 4, 5 remain
+    assert [st.get(r) is not None for r in range(6)] == [False, False, False, True, True, True]
+    assert st.used == 90 and st.evicted == 3
+    st.get(3)                       # 3 becomes the most recently used
+    st.put(6, 30, "f6")             # evicts 4
+    assert st.get(4) is None and st.get(3) == "f3" and st.get(6) == "f6"
+    assert not st.put(7, 101, "too big")
