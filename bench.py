@@ -257,11 +257,27 @@ def run_serving(device, count=4096, budget_gib=8, seed=5, load=0.8, tune_sample=
     lat = sch.run(reqs)
     bad = sum(1 for r in reqs if r.status != 0)
     s = serve.summarize(lat, reqs, max(r.done for r in reqs))
+    # the plain FP64 path on the same requests: one hqr_lstsq per request, back to back on one stream
+    nseq = min(count, 256)
+    seq_reqs = [(inputs.gaussian_device(int(m[q]), int(n[q]), 100000 + q, device),
+                 inputs.gaussian_device(int(m[q]), 1, 200000 + q, device)) for q in range(nseq)]
+    stream = torch.cuda.current_stream(device)
+    for A, B in seq_reqs[:4]:
+        h.lstsq(A.clone(), B.clone(), params, stream=stream, check=False)
+    torch.cuda.synchronize(device)
+    t0 = time.perf_counter()
+    for A, B in seq_reqs:
+        h.lstsq(A, B, params, stream=stream, check=False)
+    torch.cuda.synchronize(device)
+    seq_rate = nseq / (time.perf_counter() - t0)
+    del seq_reqs
     flops = float(sum(qr_flops(int(a), int(b)) + 4.0 * a * b for a, b in zip(m, n)))
     out = {"workload": "%d least-squares requests, rows U[256,16384], cols U[32,512], 1 rhs, Poisson arrivals" % count,
            "params": best, "budget_GiB": budget_gib, "saturated_solves_per_s": sat,
            "saturated_gflops": flops / span / 1e9, "arrival_rate_per_s": load * sat,
            "solves_per_s": s["solves_per_s"], "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"],
+           "plain_fp64_sequential_solves_per_s": seq_rate,
+           "plain_fp64_sequential_sample": "the first %d requests, one hqr_lstsq each (same tile size and tree)" % nseq,
            "batches": len(sch.batches), "mean_batch": count / len(sch.batches), "failed": bad,
            "batches_launched_while_another_ran": sum(1 for i in range(1, len(sch.batches))
                                                      if sch.batches[i]["t_launch"] < sch.batches[i - 1]["t_done"]),
