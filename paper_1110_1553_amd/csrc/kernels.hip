@@ -201,6 +201,7 @@ struct Smem {
   E T[2][IB * LDV];  // staged T blocks
   E R[IB * LDV];     // diagonal block of the killer's R (TS/TT panel kernels)
   E tau[IB];
+  V4<E> xw[8 * 64];  // partial W = V^T C of each wave (row-split panel updates)
   int task;  // index of the task taken by the workgroup (-1: launch aborted)
   int ok;    // 1 if the task's dependencies were met, 0 if the launch was aborted
 };
@@ -660,49 +661,122 @@ __device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
   lds_barrier();
 }
 
+// Row-split application of panel p inside a panel task: the strip of 16
+// columns at `strip` is shared by waves w and w + 4, wave half h = wave / 4
+// holding row blocks h NB/32 .. (h + 1) NB/32 - 1 of it in `acc`.  Each wave
+// reduces its rows' part of W = V_p^T C, the two parts are exchanged through
+// LDS and added in a fixed order (lower half + upper half, so both waves
+// hold bitwise the same W), then each wave updates its own rows; the wave of
+// the upper half (h = 0) also updates C1_p (TS/TT).  Every thread of the
+// workgroup calls this (it contains a barrier); `on` says whether the wave
+// holds a strip.
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void apply_panel_half(V4<E> (&acc)[NB / 32], const E* __restrict__ Vs,
+                                                 const E* __restrict__ Ts, int p, E* c1, int64_t ldc, const Lane& L,
+                                                 int h, bool on, V4<E>* xw) {
+  constexpr int HRB = NB / 32;
+  const int lane = threadIdx.x & 63;
+  V4<E> w0 = {E(0), E(0), E(0), E(0)}, w1 = w0, c1v = w0;
+  if (on) {
+    if (KIND != K_UNM) c1v = ld4<E>(rsrc(c1), 4 * L.g + L.q * (int)ldc);
+    const E* va = Vs + 4 * L.g * LDV + mrow<E>(L);
+#pragma unroll
+    for (int i = 0; i < HRB; ++i) {
+      const int rb = h * HRB + i;
+      if (row_block_active<E, NB, KIND>(rb, p)) {
+        E a[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = va[(16 * rb + r) * LDV];
+        w0 = mfma(a[0], acc[i][0], w0);
+        w1 = mfma(a[1], acc[i][1], w1);
+        w0 = mfma(a[2], acc[i][2], w0);
+        w1 = mfma(a[3], acc[i][3], w1);
+      }
+    }
+    xw[L.wave * 64 + lane] = w0 + w1;
+  }
+  lds_barrier();
+  if (on) {
+    const V4<E> lo = xw[(L.wave & 3) * 64 + lane], hi = xw[((L.wave & 3) + 4) * 64 + lane];
+    V4<E> w = lo + hi;
+    if (KIND != K_UNM) w += c1v;
+    E t[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t[r] = Ts[(4 * L.g + r) * LDV + mrow<E>(L)];
+    V4<E> w2t = {E(0), E(0), E(0), E(0)};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) w2t = mfma(t[r], w[r], w2t);
+    if (KIND != K_UNM && h == 0) st4(rsrc(c1), 4 * L.g + L.q * (int)ldc, c1v - w2t);
+    const V4<E> wn = -w2t;
+    const E* vc = Vs + mrow<E>(L) * LDV + 4 * L.g;
+#pragma unroll
+    for (int i = 0; i < HRB; ++i) {
+      const int rb = h * HRB + i;
+      if (row_block_active<E, NB, KIND>(rb, p)) {
+        E b0[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) b0[r] = vc[16 * rb * LDV + r];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i] = mfma(b0[r], wn[r], acc[i]);
+      }
+    }
+  }
+}
+
 // Applies panel p (V_p, T_p staged in sm.V[0], sm.T[0]) to the strips
-// p+1 .. s_last of the tile(s) (at most 3): wave w takes strip p + 1 + w.
+// p+1 .. s_last of the tile(s) (at most 3): strip p + 1 + w goes to waves w
+// and w + 4 (row halves).
 template <typename E, int NB, int KIND>
 __device__ __forceinline__ void panel_strips(E* A, E* R, int p, int s_last) {
+  constexpr int HRB = NB / 32;
   p = __builtin_amdgcn_readfirstlane(p);
   s_last = __builtin_amdgcn_readfirstlane(s_last);
   Smem<E, NB>& sm = smem<E, NB>();
   const Lane L;
-  const int s = p + 1 + L.wave;
-  if (s <= s_last) {
-    V4<E> acc[NB / 16];
-    E* strip = A + (int64_t)(16 * s) * NB;
-    load_strip<E, NB, KIND>(acc, strip, NB, p, L);
-    apply_panel<E, NB, KIND>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p,
-                          NB, L);
-    store_strip<E, NB, KIND>(acc, strip, NB, p, L);
+  const int w = L.wave & 3, h = L.wave >> 2;
+  const int s = p + 1 + w;
+  const bool on = w < 3 && s <= s_last;
+  E* strip = A + (int64_t)(16 * s) * NB;
+  V4<E> acc[HRB];
+#pragma unroll
+  for (int i = 0; i < HRB; ++i) {
+    const int rb = h * HRB + i;
+    if (on && row_block_active<E, NB, KIND>(rb, p)) acc[i] = ld4<E>(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB);
+  }
+  apply_panel_half<E, NB, KIND>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p,
+                                NB, L, h, on, sm.xw);
+#pragma unroll
+  for (int i = 0; i < HRB; ++i) {
+    const int rb = h * HRB + i;
+    if (on && row_block_active<E, NB, KIND>(rb, p)) st4(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB, acc[i]);
   }
   stores_done();
   __syncthreads();  // the next panel's column loop reads these strips from memory
 }
 
-// Left-looking update of block b (strips 4b .. 4b+3, one per wave 0-3):
-// the panels 0 .. 4b-1 of this task are applied to it, V from the tile(s)
-// already factored and T from `T`, the strips held in registers across the
-// panels.  Done right before block b is factored, so that block b depends on
-// nothing that a predecessor task writes later than its own block b.
+// Left-looking update of block b (strips 4b .. 4b+3; strip 4b + w to waves
+// w and w + 4, row halves): the panels 0 .. 4b-1 of this task are applied to
+// it, V from the tile(s) already factored and T from `T`, the strips held in
+// registers across the panels.  Done right before block b is factored, so
+// that block b depends on nothing that a predecessor task writes later than
+// its own block b.
 template <typename E, int NB, int KIND>
 __device__ __forceinline__ void panel_left_update(E* A, E* R, const E* T, int b) {
-  constexpr int NRB = NB / 16;
+  constexpr int NRB = NB / 16, HRB = NB / 32;
   b = __builtin_amdgcn_readfirstlane(b);
   Smem<E, NB>& sm = smem<E, NB>();
   const Lane L;
   const int np = 4 * b;  // panels applied
-  const bool on = L.wave < 4;
-  const int s = 4 * b + L.wave;
+  const int w = L.wave & 3, h = L.wave >> 2;
+  const int s = 4 * b + w;
   // row blocks the panels touch: UNM and TS all, TT rows < 16 np (below them,
   // a TT victim holds its own GEQRT reflectors)
   const int hi = (KIND == K_TT) ? np - 1 : NRB - 1;
   E* strip = A + (int64_t)(16 * s) * NB;
-  V4<E> acc[NRB];
+  V4<E> acc[HRB];
 #pragma unroll
-  for (int rb = 0; rb < NRB; ++rb)
-    if (on && rb <= hi) acc[rb] = ld4<E>(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB);
+  for (int i = 0; i < HRB; ++i)
+    if (h * HRB + i <= hi) acc[i] = ld4<E>(rsrc(strip), 16 * (h * HRB + i) + 4 * L.g + L.q * NB);
   PanelPrefetch<E, NB> pf;
   prefetch_panel<E, NB, KIND>(pf, A, NB, T, 0);
   for (int p = 0; p < np; ++p) {
@@ -711,12 +785,12 @@ __device__ __forceinline__ void panel_left_update(E* A, E* R, const E* T, int b)
     stage_panel<E, NB, KIND>(pf, Vs, Ts, p);
     lds_barrier();
     if (p + 1 < np) prefetch_panel<E, NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
-    if (on)
-      apply_panel<E, NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
+    apply_panel_half<E, NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB,
+                                  L, h, true, sm.xw);
   }
 #pragma unroll
-  for (int rb = 0; rb < NRB; ++rb)
-    if (on && rb <= hi) st4(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB, acc[rb]);
+  for (int i = 0; i < HRB; ++i)
+    if (h * HRB + i <= hi) st4(rsrc(strip), 16 * (h * HRB + i) + 4 * L.g + L.q * NB, acc[i]);
   stores_done();
   __syncthreads();  // the column loop of block b reads these strips from memory
 }
