@@ -89,3 +89,44 @@ def test_apply_and_lstsq_argument_checks(hqr_lib):
     assert L(vp(16), 256, 128, 256, vp(16), 256, 0, ctypes.byref(p), None, vp(16), lneed, None) == -7
     with pytest.raises(h.HQRError):
         h.apply_workspace_size(256, 0, p)
+
+
+def test_f32_ir_and_solve_argument_checks(hqr_lib):
+    import paper_1110_1553_amd as h
+    from paper_1110_1553_amd import _lib
+
+    p = h.make_params(nb=64)
+    vp = ctypes.c_void_p
+    # FP32 workspaces hold float tiles and T: smaller than the FP64 ones, larger than the float tiles alone
+    w64, w32 = h.workspace_size(512, 256, p), _lib.workspace_size_f32(512, 256, p)
+    assert 512 * 256 * 4 < w32 < w64
+    F = hqr_lib.hqr_factor_f32
+    assert F(vp(16), 100, 200, 100, ctypes.byref(p), None, vp(16), 1 << 30, None) == -2
+    assert F(vp(16), 200, 100, 150, ctypes.byref(p), None, vp(16), 1 << 30, None) == -4
+    assert F(vp(16), 512, 256, 512, ctypes.byref(p), None, vp(16), w32 - 1, None) == -8
+    # refinement
+    need = _lib.lstsq_ir_workspace_size(512, 256, p)
+    assert need > w32
+    info = _lib.IrInfo()
+    IR = hqr_lib.hqr_lstsq_ir
+    args = lambda M, N, lda, it, tol, wb: (vp(16), M, N, lda, vp(16), vp(16), None, ctypes.byref(p), None, it, tol,  # noqa: E731
+                                           vp(16), wb, None, ctypes.byref(info))
+    assert IR(*args(100, 200, 100, 30, 1e-12, need)) == -2
+    assert IR(*args(512, 256, 500, 30, 1e-12, need)) == -4
+    assert IR(*args(512, 256, 512, 0, 1e-12, need)) == -10
+    assert IR(*args(512, 256, 512, 30, -1.0, need)) == -11
+    assert IR(*args(512, 256, 512, 30, float("nan"), need)) == -11
+    assert IR(*args(512, 256, 512, 30, 1e-12, need - 1)) == -13
+    # least squares with a finished factorization: same checks as the apply entry points
+    bneed = h.apply_workspace_size(256, 3, p)
+    S = hqr_lib.hqr_solve
+    assert S(256, 128, ctypes.byref(p), None, vp(16), w64, vp(16), 200, 3, vp(16), bneed, None) == -9
+    assert S(256, 128, ctypes.byref(p), None, vp(16), w64, vp(16), 256, 0, vp(16), bneed, None) == -10
+    assert S(256, 128, ctypes.byref(p), None, vp(16), h.workspace_size(256, 128, p), vp(16), 256, 3, vp(16),
+             bneed - 1, None) == -12
+    # exporting a batch problem's factors
+    b = _lib.Batch([300, 200], [100, 200], [1, 0], p)
+    E = hqr_lib.hqr_batch_export_factors
+    assert E(b.handle, 2, vp(16), vp(16), 1 << 30, None) == -2
+    assert E(b.handle, 0, vp(16), vp(16), h.workspace_size(300, 100, p) - 1, None) == -5
+    b.close()
