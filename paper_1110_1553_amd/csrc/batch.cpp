@@ -44,6 +44,7 @@ struct hqr_batch {
   std::vector<int32_t> prob;        // problem of each task
   size_t off_info = 0, off_cnt = 0, off_desc = 0, off_tasks = 0, off_prob = 0, off_data = 0, total = 0;
   int32_t gmax = 0;                 // widest back-substitution grid (workgroups per problem)
+  int64_t max_elems = 0;            // padded elements of the largest problem (copy grid)
   void* bound_work = nullptr;       // workspace the descriptors were uploaded to
 };
 
@@ -226,6 +227,7 @@ int hqr_batch_create(int32_t count, const int64_t* M, const int64_t* N, const in
     off = align256(off + tiles * (size_t)p.nb * 16 * sizeof(double));
     d.tiles = (int64_t)off;
     off = align256(off + all * (size_t)p.nb * p.nb * sizeof(double));
+    b->max_elems = std::max<int64_t>(b->max_elems, (int64_t)all * p.nb * p.nb);
     if (b->nrhs[q] > 0) {
       const int nbc = (b->nrhs[q] + 63) / 64;
       b->gmax = std::max<int32_t>(b->gmax, nbc > 1 ? 4 * nbc : (b->nrhs[q] + 15) / 16);
@@ -301,7 +303,7 @@ int hqr_batch_run(const hqr_batch* b, void* dwork, size_t work_bytes, void* stre
   const int nb = b->p.nb;
   // control words, per-problem info and every dependency counter
   if (int rc = launch_zero_i32((int32_t*)w, (int64_t)(b->off_desc / sizeof(int32_t)), stream)) return rc;
-  if (int rc = launch_copy_batched(d, w, b->count, nb, true, stream)) return rc;
+  if (int rc = launch_copy_batched(d, w, b->count, nb, true, b->max_elems, stream)) return rc;
   if (!b->tasks.empty()) {
     LaunchArgs a{};
     a.ctrl = (int32_t*)w;
@@ -320,7 +322,7 @@ int hqr_batch_run(const hqr_batch* b, void* dwork, size_t work_bytes, void* stre
     if (int rc = launch_trsm_batched(nb, d, w, (int32_t*)w, (int32_t*)(w + b->off_info), b->count, b->gmax, stream))
       return rc;
   }
-  return launch_copy_batched(d, w, b->count, nb, false, stream);
+  return launch_copy_batched(d, w, b->count, nb, false, b->max_elems, stream);
 }
 
 int hqr_batch_status(const hqr_batch* b, const void* dwork, void* stream, double timeout_s, int32_t* status,

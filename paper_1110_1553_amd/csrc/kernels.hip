@@ -795,6 +795,71 @@ __device__ __forceinline__ void panel_left_update(E* A, E* R, const E* T, int b)
   __syncthreads();  // the column loop of block b reads these strips from memory
 }
 
+// FP32 variants of panel_strips and panel_left_update without the row
+// split (one strip per wave, waves 0-3): inlined into the float panel task
+// the row-split versions make the register allocator spill.
+//
+// Applies panel p (V_p, T_p staged in sm.V[0], sm.T[0]) to the strips
+// p+1 .. s_last of the tile(s) (at most 3): wave w takes strip p + 1 + w.
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void panel_strips_4w(E* A, E* R, int p, int s_last) {
+  p = __builtin_amdgcn_readfirstlane(p);
+  s_last = __builtin_amdgcn_readfirstlane(s_last);
+  Smem<E, NB>& sm = smem<E, NB>();
+  const Lane L;
+  const int s = p + 1 + L.wave;
+  if (s <= s_last) {
+    V4<E> acc[NB / 16];
+    E* strip = A + (int64_t)(16 * s) * NB;
+    load_strip<E, NB, KIND>(acc, strip, NB, p, L);
+    apply_panel<E, NB, KIND>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p,
+                          NB, L);
+    store_strip<E, NB, KIND>(acc, strip, NB, p, L);
+  }
+  stores_done();
+  __syncthreads();  // the next panel's column loop reads these strips from memory
+}
+
+// Left-looking update of block b (strips 4b .. 4b+3, one per wave 0-3):
+// the panels 0 .. 4b-1 of this task are applied to it, V from the tile(s)
+// already factored and T from `T`, the strips held in registers across the
+// panels.  Done right before block b is factored, so that block b depends on
+// nothing that a predecessor task writes later than its own block b.
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void panel_left_update_4w(E* A, E* R, const E* T, int b) {
+  constexpr int NRB = NB / 16;
+  b = __builtin_amdgcn_readfirstlane(b);
+  Smem<E, NB>& sm = smem<E, NB>();
+  const Lane L;
+  const int np = 4 * b;  // panels applied
+  const bool on = L.wave < 4;
+  const int s = 4 * b + L.wave;
+  // row blocks the panels touch: UNM and TS all, TT rows < 16 np (below them,
+  // a TT victim holds its own GEQRT reflectors)
+  const int hi = (KIND == K_TT) ? np - 1 : NRB - 1;
+  E* strip = A + (int64_t)(16 * s) * NB;
+  V4<E> acc[NRB];
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb)
+    if (on && rb <= hi) acc[rb] = ld4<E>(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB);
+  PanelPrefetch<E, NB> pf;
+  prefetch_panel<E, NB, KIND>(pf, A, NB, T, 0);
+  for (int p = 0; p < np; ++p) {
+    E* Vs = sm.V[p & 1];
+    E* Ts = sm.T[p & 1];
+    stage_panel<E, NB, KIND>(pf, Vs, Ts, p);
+    lds_barrier();
+    if (p + 1 < np) prefetch_panel<E, NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
+    if (on)
+      apply_panel<E, NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
+  }
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb)
+    if (on && rb <= hi) st4(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB, acc[rb]);
+  stores_done();
+  __syncthreads();  // the column loop of block b reads these strips from memory
+}
+
 // ---------------------------------------------------------------------------
 // Scheduler steps.
 
@@ -1041,10 +1106,20 @@ __device__ __noinline__ int panel_task(const LaunchArgs& a, int t, const DevTask
       __builtin_amdgcn_s_setprio(0);
       return 0;
     }
-    if (b > 0) panel_left_update<E, NB, KIND>(A, R, T, b);
+    if (b > 0) {
+      if constexpr (sizeof(E) == 4)
+        panel_left_update_4w<E, NB, KIND>(A, R, T, b);
+      else
+        panel_left_update<E, NB, KIND>(A, R, T, b);
+    }
     for (int p = 4 * b; p < 4 * b + 4; ++p) {
       panel_columns<E, NB, KIND>(A, R, T, p);
-      if (p < 4 * b + 3) panel_strips<E, NB, KIND>(A, R, p, 4 * b + 3);
+      if (p < 4 * b + 3) {
+        if constexpr (sizeof(E) == 4)
+          panel_strips_4w<E, NB, KIND>(A, R, p, 4 * b + 3);
+        else
+          panel_strips<E, NB, KIND>(A, R, p, 4 * b + 3);
+      }
     }
     if (b + 1 < active) {
       release_block<E, NB>(a, task, b);
@@ -1605,9 +1680,14 @@ int launch_trsm_f32(int nb, const float* R, float* Y, int cpt, int32_t* ctrl, in
   return launch_trsm_t<float>(nb, R, Y, cpt, ctrl, N, mt, nt, nbc, groups, stream);
 }
 
-int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, void* stream) {
+int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, int64_t max_elems, void* stream) {
   if (count <= 0) return 0;
-  hipLaunchKernelGGL(copy_batched_kernel, dim3(256, count), dim3(256), 0, (hipStream_t)stream, d, w, nb, in ? 1 : 0);
+  // workgroups per problem: enough for about 8 elements per thread of the largest problem
+  int64_t gx = (max_elems + 2047) / 2048;
+  if (gx < 1) gx = 1;
+  if (gx > 4096) gx = 4096;
+  hipLaunchKernelGGL(copy_batched_kernel, dim3((unsigned)gx, count), dim3(256), 0, (hipStream_t)stream, d, w, nb,
+                     in ? 1 : 0);
   return record_hip(hipGetLastError(), "copy_batched_kernel launch");
 }
 

@@ -93,7 +93,9 @@ const char* last_error();
 // matrices and right-hand sides into their tiles (in) or A and B back out;
 // back substitution of every problem's right-hand sides (first zero
 // diagonal entry j of problem q recorded as info[q] = max(N - j)).
-int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, void* stream);
+// max_elems: padded elements (matrix and right-hand sides) of the largest
+// problem, which sizes the copy grid.
+int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, int64_t max_elems, void* stream);
 int launch_trsm_batched(int nb, const ProbDesc* d, char* w, int32_t* ctrl, int32_t* info, int count, int gmax,
                         void* stream);
 
