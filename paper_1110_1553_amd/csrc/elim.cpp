@@ -446,24 +446,83 @@ int build_plan(int32_t mt, int32_t nt, const hqr_params& prm, int order, int chu
     plan.prio.swap(prio);
     return 0;
   }
-  // list schedule: repeatedly take the ready task with the longest remaining path
+  // Dispatch order: a list schedule simulated on kSimWorkers workers with
+  // estimated task durations.  A task becomes ready when its predecessors
+  // have finished in simulated time, and a free worker takes the ready task
+  // with the longest remaining path (in the same time estimate).  Listing
+  // tasks in this order keeps workgroups from taking tasks whose inputs are
+  // far from ready (a plain topological order by path length lists whole
+  // dependency chains back to back, and the workgroups that take them wait on
+  // each other).  Durations (microseconds at nb = 256, from measurements of
+  // the tile kernels): panel tasks are latency bound (~470 us for a full
+  // tile, proportional to nb), update tasks scale with their flops, plus a
+  // fixed per-task cost.  A panel task publishes its tile block by block, so
+  // the panel tasks that depend on it can start one block after it starts;
+  // every other successor waits for its end.
+  constexpr int kSimWorkers = 256;
+  const double s = prm.nb / 256.0;
+  std::vector<double> dur(nd), bl(nd, 0.0);
+  for (int64_t i = 0; i < nd; ++i) {
+    const int op = dev[i].op;
+    if (op == GEQRT || op == TSQRT || op == TTQRT) {
+      dur[i] = 470.0 * s * (double)dev[i].chunk / chunks + 10.0;
+    } else {
+      const double per_unit = (op == TSMQR) ? 6.5 : 8.7;  // TSMQR runs closest to the MFMA rate
+      dur[i] = per_unit * (double)wt[i] * s * s * s + 8.0;
+    }
+  }
+  auto is_panel = [&](int64_t i) { return dev[i].op == GEQRT || dev[i].op == TSQRT || dev[i].op == TTQRT; };
+  std::vector<double> lead(nd);  // time after its start at which a panel task's panel successors may start
+  for (int64_t i = 0; i < nd; ++i) lead[i] = is_panel(i) ? dur[i] / std::max<int>(1, dev[i].chunk) : dur[i];
+  for (int64_t i = nd - 1; i >= 0; --i) {
+    double best = dur[i];
+    for (int64_t q = nsucc[i]; q < nsucc[i + 1]; ++q) {
+      const int64_t j = succ[q];
+      best = std::max(best, (is_panel(i) && is_panel(j) ? lead[i] : dur[i]) + bl[j]);
+    }
+    bl[i] = best;
+  }
   std::vector<int32_t> indeg(nd, 0);
   for (int64_t i = 0; i < nd; ++i) indeg[i] = (int32_t)(pred_off[i + 1] - pred_off[i]);
-  typedef std::pair<int64_t, int64_t> Key;  // (priority, -index)
+  typedef std::pair<double, int64_t> Key;  // (remaining path, -index)
   std::priority_queue<Key> ready;
+  // events: (time, task, kind) with kind 0 = the first block of a panel task
+  // is published (its panel successors), 1 = the task ends
+  typedef std::tuple<double, int64_t, int> Event;
+  std::priority_queue<Event, std::vector<Event>, std::greater<Event>> running;
   for (int64_t i = 0; i < nd; ++i)
-    if (indeg[i] == 0) ready.push({prio[i], -i});
+    if (indeg[i] == 0) ready.push({bl[i], -i});
   plan.dev.reserve(nd);
   plan.prio.reserve(nd);
-  while (!ready.empty()) {
-    const int64_t i = -ready.top().second;
-    ready.pop();
-    plan.dev.push_back(dev[i]);
-    plan.prio.push_back(prio[i]);
-    for (int64_t q = nsucc[i]; q < nsucc[i + 1]; ++q)
-      if (--indeg[succ[q]] == 0) ready.push({prio[succ[q]], -succ[q]});
+  int free_workers = kSimWorkers;
+  double now = 0.0;
+  while ((int64_t)plan.dev.size() < nd) {
+    while (free_workers > 0 && !ready.empty()) {
+      const int64_t i = -ready.top().second;
+      ready.pop();
+      plan.dev.push_back(dev[i]);
+      plan.prio.push_back((int64_t)(bl[i] * 16.0));
+      if (is_panel(i)) running.push(Event{now + lead[i], i, 0});
+      running.push(Event{now + dur[i], i, 1});
+      --free_workers;
+    }
+    if ((int64_t)plan.dev.size() == nd) break;
+    if (running.empty()) return HQR_ERR_INTERNAL;  // a dependency cycle (cannot happen: edges point forward)
+    now = std::get<0>(running.top());
+    while (!running.empty() && std::get<0>(running.top()) <= now) {
+      const int64_t j = std::get<1>(running.top());
+      const int kind = std::get<2>(running.top());
+      running.pop();
+      if (kind == 1) ++free_workers;
+      for (int64_t q = nsucc[j]; q < nsucc[j + 1]; ++q) {
+        const int64_t sq = succ[q];
+        // panel -> panel edges are released by the first-block event, the others at the end
+        const bool early = is_panel(j) && is_panel(sq);
+        if (early != (kind == 0)) continue;
+        if (--indeg[sq] == 0) ready.push({bl[sq], -sq});
+      }
+    }
   }
-  if ((int64_t)plan.dev.size() != nd) return HQR_ERR_INTERNAL;
   return 0;
 }
 
