@@ -509,7 +509,9 @@ __device__ __forceinline__ double readlane(double v, int lane) {
 // published through LDS (double buffered), which costs one workgroup
 // barrier per column.  Leaves V_p in sm.V[0] (with the structure of the
 // kind), T_p in sm.T[0] and in `T`, and the factored columns in A (and R).
-template <typename E, int NB, int KIND>
+// XL: the panel's columns are taken from sm.V[0] (row-major, stride LDV,
+// left there by panel_block) instead of from memory.
+template <typename E, int NB, int KIND, bool XL = false>
 __device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
   constexpr int NM = NB / 16;  // row slots per thread
   p = __builtin_amdgcn_readfirstlane(p);  // uniform: row-slot guards become scalar branches
@@ -536,7 +538,7 @@ __device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
     const int r = base + q + 16 * m;
     // TT: rows below the diagonal hold the tile's own GEQRT reflectors
     const bool act = ct && m < nm && (KIND != K_TT || r <= c0 + cc);
-    x[m] = act ? gload(col + r) : E(0);
+    x[m] = act ? (XL ? sm.V[0][r * LDV + cc] : gload(col + r)) : E(0);
   }
   E rv = E(0);  // TS/TT: R(c0 + q, c0 + cc) of the killer's diagonal block
   if (KIND != K_UNM && ct && q <= cc) rv = gload(R + (c0 + q) + (int64_t)(c0 + cc) * NB);
@@ -793,6 +795,69 @@ __device__ __forceinline__ void panel_left_update(E* A, E* R, const E* T, int b)
     if (h * HRB + i <= hi) st4(rsrc(strip), 16 * (h * HRB + i) + 4 * L.g + L.q * NB, acc[i]);
   stores_done();
   __syncthreads();  // the column loop of block b reads these strips from memory
+}
+
+// Block b of a panel task (columns 64b .. 64b+63) with its four strips
+// kept in registers from start to end: strip 4b + w lives in waves w and
+// w + 4 (row halves).  The strips are loaded once, receive this task's
+// earlier panels (left-looking), and then for each panel p of the block the
+// strip of p is handed to the column loop through LDS (sm.V[0]) and the
+// panel is applied to the block's later strips in registers; the factored
+// columns reach memory through the column loop (GEQRT: the rows of a strip
+// above its diagonal block, which the column loop does not cover, are
+// stored at the hand-over).  No strip goes through memory between the
+// panels of a block.
+template <typename E, int NB, int KIND>
+__device__ __forceinline__ void panel_block(E* A, E* R, E* T, int b) {
+  constexpr int HRB = NB / 32;
+  b = __builtin_amdgcn_readfirstlane(b);
+  Smem<E, NB>& sm = smem<E, NB>();
+  const Lane L;
+  const int w = L.wave & 3, h = L.wave >> 2;
+  const int s = 4 * b + w;   // this wave's strip
+  const int np = 4 * b;      // earlier panels of this task
+  // row blocks held: TT rows up to the block's last diagonal block (below
+  // them a TT victim holds its own GEQRT reflectors), otherwise all
+  const int hi = (KIND == K_TT) ? 4 * b + 3 : NB / 16 - 1;
+  E* strip = A + (int64_t)(16 * s) * NB;
+  E* c1s = KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB;  // killer's strip s
+  V4<E> acc[HRB];
+#pragma unroll
+  for (int i = 0; i < HRB; ++i)
+    if (h * HRB + i <= hi) acc[i] = ld4<E>(rsrc(strip), 16 * (h * HRB + i) + 4 * L.g + L.q * NB);
+  if (np > 0) {
+    PanelPrefetch<E, NB> pf;
+    prefetch_panel<E, NB, KIND>(pf, A, NB, T, 0);
+    for (int p = 0; p < np; ++p) {
+      E* Vs = sm.V[p & 1];
+      E* Ts = sm.T[p & 1];
+      stage_panel<E, NB, KIND>(pf, Vs, Ts, p);
+      lds_barrier();
+      if (p + 1 < np) prefetch_panel<E, NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
+      apply_panel_half<E, NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : c1s + 16 * p, NB, L, h, true, sm.xw);
+    }
+  }
+  for (int p = 4 * b; p < 4 * b + 4; ++p) {
+    lds_barrier();  // every wave is done with the V panel and T in sm.V[0], sm.T[0]
+    if (s == p) {
+      E* H = sm.V[0];
+#pragma unroll
+      for (int i = 0; i < HRB; ++i) {
+        const int rb = h * HRB + i;
+        if (rb <= hi) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) H[(16 * rb + 4 * L.g + r) * LDV + L.q] = acc[i][r];
+          // GEQRT: rows above the diagonal block are final R entries
+          if (KIND == K_UNM && rb < p) st4(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB, acc[i]);
+        }
+      }
+    }
+    lds_barrier();
+    panel_columns<E, NB, KIND, true>(A, R, T, p);
+    if (p < 4 * b + 3)
+      apply_panel_half<E, NB, KIND>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : c1s + 16 * p, NB, L, h, s > p,
+                                    sm.xw);
+  }
 }
 
 // FP32 variants of panel_strips and panel_left_update without the row
@@ -1106,20 +1171,14 @@ __device__ __noinline__ int panel_task(const LaunchArgs& a, int t, const DevTask
       __builtin_amdgcn_s_setprio(0);
       return 0;
     }
-    if (b > 0) {
-      if constexpr (sizeof(E) == 4)
-        panel_left_update_4w<E, NB, KIND>(A, R, T, b);
-      else
-        panel_left_update<E, NB, KIND>(A, R, T, b);
-    }
-    for (int p = 4 * b; p < 4 * b + 4; ++p) {
-      panel_columns<E, NB, KIND>(A, R, T, p);
-      if (p < 4 * b + 3) {
-        if constexpr (sizeof(E) == 4)
-          panel_strips_4w<E, NB, KIND>(A, R, p, 4 * b + 3);
-        else
-          panel_strips<E, NB, KIND>(A, R, p, 4 * b + 3);
+    if constexpr (sizeof(E) == 4) {
+      if (b > 0) panel_left_update_4w<E, NB, KIND>(A, R, T, b);
+      for (int p = 4 * b; p < 4 * b + 4; ++p) {
+        panel_columns<E, NB, KIND>(A, R, T, p);
+        if (p < 4 * b + 3) panel_strips_4w<E, NB, KIND>(A, R, p, 4 * b + 3);
       }
+    } else {
+      panel_block<E, NB, KIND>(A, R, T, b);
     }
     if (b + 1 < active) {
       release_block<E, NB>(a, task, b);
