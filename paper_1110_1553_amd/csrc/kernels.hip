@@ -483,12 +483,11 @@ __device__ __forceinline__ void run_update(Smem<E, NB>& sm, const E* V, const E*
 // otherwise beta = -sign(alpha) sqrt(alpha^2 + s^2), tau = (beta - alpha)/beta,
 // tail /= (alpha - beta), head = beta.
 //
-// The tile is processed in blocks of 64 columns (four 16-column panels).
-// Inside a block each panel is factored (panel_columns) and applied to the
-// block's remaining strips (panel_strips); at the end of a block its four
-// panels are applied to the columns right of the block, one strip per wave
-// held in registers across the four panels (panel_block_update), so those
-// columns are read and written once per block instead of once per panel.
+// The tile is processed in blocks of 64 columns (four 16-column panels),
+// left-looking: a block first receives the task's earlier panels, then each
+// of its panels is factored (panel_columns) and applied to the block's
+// remaining strips (panel_block; panel_left_update_4w and panel_strips_4w
+// for FP32).
 
 // Reads lane `lane` (wave-uniform) of a double held in VGPRs.
 __device__ __forceinline__ float readlane(float v, int lane) {
@@ -725,78 +724,6 @@ __device__ __forceinline__ void apply_panel_half(V4<E> (&acc)[NB / 32], const E*
   }
 }
 
-// Applies panel p (V_p, T_p staged in sm.V[0], sm.T[0]) to the strips
-// p+1 .. s_last of the tile(s) (at most 3): strip p + 1 + w goes to waves w
-// and w + 4 (row halves).
-template <typename E, int NB, int KIND>
-__device__ __forceinline__ void panel_strips(E* A, E* R, int p, int s_last) {
-  constexpr int HRB = NB / 32;
-  p = __builtin_amdgcn_readfirstlane(p);
-  s_last = __builtin_amdgcn_readfirstlane(s_last);
-  Smem<E, NB>& sm = smem<E, NB>();
-  const Lane L;
-  const int w = L.wave & 3, h = L.wave >> 2;
-  const int s = p + 1 + w;
-  const bool on = w < 3 && s <= s_last;
-  E* strip = A + (int64_t)(16 * s) * NB;
-  V4<E> acc[HRB];
-#pragma unroll
-  for (int i = 0; i < HRB; ++i) {
-    const int rb = h * HRB + i;
-    if (on && row_block_active<E, NB, KIND>(rb, p)) acc[i] = ld4<E>(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB);
-  }
-  apply_panel_half<E, NB, KIND>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p,
-                                NB, L, h, on, sm.xw);
-#pragma unroll
-  for (int i = 0; i < HRB; ++i) {
-    const int rb = h * HRB + i;
-    if (on && row_block_active<E, NB, KIND>(rb, p)) st4(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB, acc[i]);
-  }
-  stores_done();
-  __syncthreads();  // the next panel's column loop reads these strips from memory
-}
-
-// Left-looking update of block b (strips 4b .. 4b+3; strip 4b + w to waves
-// w and w + 4, row halves): the panels 0 .. 4b-1 of this task are applied to
-// it, V from the tile(s) already factored and T from `T`, the strips held in
-// registers across the panels.  Done right before block b is factored, so
-// that block b depends on nothing that a predecessor task writes later than
-// its own block b.
-template <typename E, int NB, int KIND>
-__device__ __forceinline__ void panel_left_update(E* A, E* R, const E* T, int b) {
-  constexpr int NRB = NB / 16, HRB = NB / 32;
-  b = __builtin_amdgcn_readfirstlane(b);
-  Smem<E, NB>& sm = smem<E, NB>();
-  const Lane L;
-  const int np = 4 * b;  // panels applied
-  const int w = L.wave & 3, h = L.wave >> 2;
-  const int s = 4 * b + w;
-  // row blocks the panels touch: UNM and TS all, TT rows < 16 np (below them,
-  // a TT victim holds its own GEQRT reflectors)
-  const int hi = (KIND == K_TT) ? np - 1 : NRB - 1;
-  E* strip = A + (int64_t)(16 * s) * NB;
-  V4<E> acc[HRB];
-#pragma unroll
-  for (int i = 0; i < HRB; ++i)
-    if (h * HRB + i <= hi) acc[i] = ld4<E>(rsrc(strip), 16 * (h * HRB + i) + 4 * L.g + L.q * NB);
-  PanelPrefetch<E, NB> pf;
-  prefetch_panel<E, NB, KIND>(pf, A, NB, T, 0);
-  for (int p = 0; p < np; ++p) {
-    E* Vs = sm.V[p & 1];
-    E* Ts = sm.T[p & 1];
-    stage_panel<E, NB, KIND>(pf, Vs, Ts, p);
-    lds_barrier();
-    if (p + 1 < np) prefetch_panel<E, NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
-    apply_panel_half<E, NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB,
-                                  L, h, true, sm.xw);
-  }
-#pragma unroll
-  for (int i = 0; i < HRB; ++i)
-    if (h * HRB + i <= hi) st4(rsrc(strip), 16 * (h * HRB + i) + 4 * L.g + L.q * NB, acc[i]);
-  stores_done();
-  __syncthreads();  // the column loop of block b reads these strips from memory
-}
-
 // Block b of a panel task (columns 64b .. 64b+63) with its four strips
 // kept in registers from start to end: strip 4b + w lives in waves w and
 // w + 4 (row halves).  The strips are loaded once, receive this task's
@@ -860,9 +787,9 @@ __device__ __forceinline__ void panel_block(E* A, E* R, E* T, int b) {
   }
 }
 
-// FP32 variants of panel_strips and panel_left_update without the row
-// split (one strip per wave, waves 0-3): inlined into the float panel task
-// the row-split versions make the register allocator spill.
+// FP32 panel tasks take the block in the form below instead (strips
+// through memory between panels, one wave per strip): the register-resident
+// form above makes the float register allocation spill.
 //
 // Applies panel p (V_p, T_p staged in sm.V[0], sm.T[0]) to the strips
 // p+1 .. s_last of the tile(s) (at most 3): wave w takes strip p + 1 + w.
