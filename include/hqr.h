@@ -251,7 +251,7 @@ int hqr_lstsq_workspace_size(int64_t M, int64_t N, int32_t nrhs, const hqr_param
  * so the update kernels transform it by Q^T inside the same persistent
  * launch (no second pass over the Householder vectors); then
  * x = R^{-1} (Q^T B)(0:N) by back substitution with the leading N x N block
- * of R (one launch per tile row).  On return (after the stream) A holds the
+ * of R (one launch, a workgroup per right-hand-side column).  On return (after the stream) A holds the
  * factorization as after hqr_factor, B(0:N, :) the solutions and B(N:M, :)
  * the components of Q^T B whose norm is the residual norm.  dwork:
  * hqr_lstsq_workspace_size bytes; it also holds Q's factors for

@@ -394,11 +394,8 @@ int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t
   char* w = (char*)dwork;
   const double* tiles = (const double*)(w + L.tiles);
   double* Bt = (double*)(w + L.tiles) + (size_t)L.mt * L.nt * p.nb * p.nb;
-  const int nbc = (nrhs + 63) / 64;
-  const int groups = nbc > 1 ? 4 : (nrhs + 15) / 16;
-  // the right-hand sides are tile columns of nb: nb / 64 blocks of 64 columns each
-  if ((rc = launch_trsm(p.nb, tiles, Bt, p.nb / 64, (int32_t*)(w + L.ctrl), N, L.mt, L.nt, nbc, groups, stream)))
-    return rc;
+  // the right-hand sides are tile columns of nb after the matrix tiles
+  if ((rc = launch_trsv(p.nb, tiles, Bt, p.nb, (int32_t*)(w + L.ctrl), N, L.mt, nrhs, stream))) return rc;
   return launch_tile_copy(dB, ldb, Bt, M, nrhs, p.nb, p.nb, L.mt, L.nrt, false, stream);
 }
 
@@ -415,9 +412,7 @@ int hqr_solve(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* ex
   char* bw = (char*)bwork;
   double* Bb = (double*)(bw + AL.blocks);
   const double* tiles = (const double*)((const char*)dwork + L.tiles);
-  const int groups = AL.nbc > 1 ? 4 : (nrhs + 15) / 16;
-  if ((rc = launch_trsm(p.nb, tiles, Bb, 1, (int32_t*)(bw + AL.ctrl), N, L.mt, L.nt, AL.nbc, groups, stream)))
-    return rc;
+  if ((rc = launch_trsv(p.nb, tiles, Bb, 64, (int32_t*)(bw + AL.ctrl), N, L.mt, nrhs, stream))) return rc;
   return launch_tile_copy(dB, ldb, Bb, M, nrhs, p.nb, 64, AL.mt, AL.nbc, false, stream);
 }
 

@@ -43,7 +43,7 @@ struct hqr_batch {
   std::vector<hqr::DevTask> tasks;  // merged dispatch order
   std::vector<int32_t> prob;        // problem of each task
   size_t off_info = 0, off_cnt = 0, off_desc = 0, off_tasks = 0, off_prob = 0, off_data = 0, total = 0;
-  int32_t gmax = 0;                 // widest back-substitution grid (workgroups per problem)
+  int32_t max_nrhs = 0;             // widest back substitution (workgroups per problem)
   int64_t max_elems = 0;            // padded elements of the largest problem (copy grid)
   void* bound_work = nullptr;       // workspace the descriptors were uploaded to
 };
@@ -228,10 +228,7 @@ int hqr_batch_create(int32_t count, const int64_t* M, const int64_t* N, const in
     d.tiles = (int64_t)off;
     off = align256(off + all * (size_t)p.nb * p.nb * sizeof(double));
     b->max_elems = std::max<int64_t>(b->max_elems, (int64_t)all * p.nb * p.nb);
-    if (b->nrhs[q] > 0) {
-      const int nbc = (b->nrhs[q] + 63) / 64;
-      b->gmax = std::max<int32_t>(b->gmax, nbc > 1 ? 4 * nbc : (b->nrhs[q] + 15) / 16);
-    }
+    b->max_nrhs = std::max<int32_t>(b->max_nrhs, b->nrhs[q]);
   }
   b->total = off;
   *out = b.release();
@@ -318,8 +315,9 @@ int hqr_batch_run(const hqr_batch* b, void* dwork, size_t work_bytes, void* stre
     const int workers = b->ex.workers > 0 ? b->ex.workers : default_workers(nb);
     if (int rc = launch_persistent(nb, a, workers, stream)) return rc;
   }
-  if (b->gmax > 0) {
-    if (int rc = launch_trsm_batched(nb, d, w, (int32_t*)w, (int32_t*)(w + b->off_info), b->count, b->gmax, stream))
+  if (b->max_nrhs > 0) {
+    if (int rc = launch_trsv_batched(nb, d, w, (int32_t*)w, (int32_t*)(w + b->off_info), b->count, b->max_nrhs,
+                                     stream))
       return rc;
   }
   return launch_copy_batched(d, w, b->count, nb, false, b->max_elems, stream);

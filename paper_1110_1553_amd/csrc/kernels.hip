@@ -1268,113 +1268,95 @@ __global__ void copy_batched_kernel(const ProbDesc* descs, char* w, int nb, int 
 }
 
 // ---------------------------------------------------------------------------
-// Back substitution R x = y for tile row i of the leading N x N triangle
-// (least squares after B <- Q^T B).  R: the factored tiles (nb x nb,
-// tile-contiguous), Y: B in blocks of nb x 64; x overwrites y.  One
-// workgroup per (64-column block of B, group of 16 columns); thread r owns
-// row r of the tile row.  Rows at or beyond N are neither solved nor
-// written; x_j of rows >= N counts as zero.
-//   z = y_i - sum_{j > i} R_ij x_j           (x_j staged through LDS)
-//   z -> R_ii^{-1} z, 16 rows at a time: lanes 0..15 of wave 0 solve the
-//   16 x 16 diagonal block (lane = column), the rows above subtract it.
-// A zero diagonal entry R_jj is recorded in ctrl (status HQR_ERR_SINGULAR,
-// *info = max over such j of N - j; nword, when not null, receives N).
-template <typename E, int NB>
-__device__ void trsm_tile_row(const E* R, E* Y, int cpt, int32_t* ctrl, int32_t* info, int32_t* nword,
-                              int64_t N, int mt, int nt, int i, int blk, int grp) {
-  E* xs = reinterpret_cast<E*>(hqr_lds);  // x_j or z of this tile row: NB rows x 16 columns, stride 17 (dynamic LDS)
-  const int r = threadIdx.x;
-  const int64_t row0 = (int64_t)i * NB;
-  const int nv = (int)((N - row0) < NB ? (N - row0) : NB);  // rows of this tile row inside N
-  // Y: tile columns of 64 cpt columns; block blk = chunk blk % cpt of tile column blk / cpt
-  const int64_t rstride = (int64_t)NB * 64 * cpt;  // from one tile row of Y to the next
-  E* Yb = Y + (int64_t)(blk / cpt) * mt * rstride + (int64_t)(64 * (blk % cpt) + 16 * grp) * NB;
-  E z[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) z[c] = Yb[(int64_t)i * rstride + r + (int64_t)c * NB];
-  for (int j = i + 1; j < nt; ++j) {
-    const int64_t jrow0 = (int64_t)j * NB;
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const E xv = Yb[(int64_t)j * rstride + r + (int64_t)c * NB];
-      xs[r * 17 + c] = (jrow0 + r < N) ? xv : E(0);
+// Back substitution R x = y with the leading N x N triangle of the factored
+// tiles R (tile (i, j) at (j mt + i) NB^2, column-major, leading dimension
+// NB), one right-hand-side column c per workgroup of 256 threads.  y is
+// column c of a blocked matrix with cw columns per block (block (i, jb) at
+// Y + (jb mt + i) NB cw, column-major with leading dimension NB): the tile
+// columns of B appended to the factorization (cw = NB) or the blocks of B
+// of the apply path (cw = 64).  x overwrites y in rows 0 .. N-1.
+// Unknowns are taken 64 at a time from the bottom: the 64 x 64 diagonal
+// triangle is staged in LDS and solved by one wave (lane = unknown, one
+// shuffle per step), then all threads remove the block from the rows above
+// it.  A zero diagonal entry R_jj is recorded in ctrl (status
+// HQR_ERR_SINGULAR, *info = max over such j of N - j; nword, when not null,
+// receives N).
+template <int NB>
+__device__ void trsv_column(const double* R, double* Y, int cw, int mt, int64_t N, int c, int32_t* ctrl,
+                            int32_t* info, int32_t* nword) {
+  __shared__ double xb[64];
+  __shared__ double Rd[64 * 65];  // Rd[i * 65 + j] = R(k0 + i, k0 + j)
+  double* y = Y + (int64_t)(c / cw) * mt * NB * cw + (int64_t)(c % cw) * NB;
+  const int64_t rs = (int64_t)NB * cw;  // from one tile row of y to the next
+  const int64_t tsz = (int64_t)NB * NB;
+  const int t = threadIdx.x, lane = t & 63;
+  const int64_t nblk = (N + 63) / 64;
+  for (int64_t bi = nblk - 1; bi >= 0; --bi) {
+    const int64_t k0 = bi * 64;
+    const int nv = (int)((N - k0) < 64 ? (N - k0) : 64);
+    const int64_t kt = k0 / NB, ko = k0 - kt * NB;  // the 64 rows / columns lie in tile row / column kt
+    const double* Rkk = R + (kt * mt + kt) * tsz + ko + ko * NB;
+    for (int e = t; e < 64 * 64; e += 256) {
+      const int i = e & 63, j = e >> 6;
+      Rd[i * 65 + j] = (i < nv && j < nv && i <= j) ? Rkk[i + (int64_t)j * NB] : 0.0;
     }
+    double* yk = y + kt * rs + ko;  // y(k0)
     __syncthreads();
-    const E* Rij = R + ((int64_t)j * mt + i) * NB * NB + r;
-    for (int k = 0; k < NB; ++k) {
-      const E rk = Rij[(int64_t)k * NB];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) z[c] -= rk * xs[k * 17 + c];
-    }
-  }
-  const E* Rii = R + ((int64_t)i * mt + i) * NB * NB;
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < 16; ++c) xs[r * 17 + c] = z[c];
-  __syncthreads();
-  for (int b = (nv - 1) / 16; b >= 0; --b) {
-    const int r0 = 16 * b;
-    if (r < 16) {
-      const int c = r;  // lane = column
-      for (int rr = r0 + 15; rr >= r0; --rr) {
-        if (rr >= nv) continue;
-        E t = xs[rr * 17 + c];
-        for (int k = rr + 1; k < r0 + 16 && k < nv; ++k) t -= Rii[rr + (int64_t)k * NB] * xs[k * 17 + c];
-        const E d = Rii[rr + (int64_t)rr * NB];
-        if (d == E(0) && c == 0) {
+    if (t < 64) {
+      double v = lane < nv ? yk[lane] : 0.0;
+      for (int s = nv - 1; s >= 0; --s) {
+        const double dg = Rd[s * 65 + s];
+        if (dg == 0.0 && lane == s) {
           int32_t none = 0;
           __hip_atomic_compare_exchange_strong(&ctrl[1], &none, (int32_t)HQR_ERR_SINGULAR, __ATOMIC_RELAXED,
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_fetch_max(info, (int32_t)(N - (row0 + rr)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_max(info, (int32_t)(N - (k0 + s)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (nword) __hip_atomic_store(nword, (int32_t)N, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        xs[rr * 17 + c] = t / d;
+        const double xs = __shfl(v, s) / dg;
+        if (lane == s) v = xs;
+        if (lane < s) v -= Rd[lane * 65 + s] * xs;
       }
+      xb[lane] = v;
+      if (lane < nv) yk[lane] = v;
     }
     __syncthreads();
-    if (r < r0) {
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        E t = xs[r * 17 + c];
-        for (int k = r0; k < r0 + 16 && k < nv; ++k) t -= Rii[r + (int64_t)k * NB] * xs[k * 17 + c];
-        xs[r * 17 + c] = t;
+    // rows above the block: y(a) -= sum_s R(a, k0 + s) x_s
+    for (int64_t a = t; a < k0; a += 256) {
+      const int64_t at = a / NB, ao = a - at * NB;
+      const double* ra = R + (kt * mt + at) * tsz + ao + ko * NB;  // R(a, k0)
+      double acc0 = 0.0, acc1 = 0.0;
+      int s = 0;
+      for (; s + 1 < nv; s += 2) {
+        acc0 += ra[(int64_t)s * NB] * xb[s];
+        acc1 += ra[(int64_t)(s + 1) * NB] * xb[s + 1];
       }
+      if (s < nv) acc0 += ra[(int64_t)s * NB] * xb[s];
+      y[at * rs + ao] -= acc0 + acc1;
     }
     __syncthreads();
   }
-  if (r < nv) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c) Yb[(int64_t)i * rstride + r + (int64_t)c * NB] = xs[r * 17 + c];
-  }
 }
 
-// Tile row i of one problem; workgroup x = (64-column block, group of 16).
-// A zero diagonal entry sets ctrl[6] = max(N - j) and ctrl[7] = N.
-template <typename E, int NB>
-__global__ __launch_bounds__(NB) void trsm_tile_row_kernel(const E* R, E* Y, int cpt, int32_t* ctrl,
-                                                           int64_t N, int mt, int nt, int i, int groups) {
-  trsm_tile_row<E, NB>(R, Y, cpt, ctrl, &ctrl[6], &ctrl[7], N, mt, nt, i, blockIdx.x / groups, blockIdx.x % groups);
-}
-
-// Every tile row of every problem of a batch in one launch: workgroup
-// (x, q) solves one group of 16 right-hand-side columns of problem q from
-// the last tile row up; it reads back only the rows of x it wrote itself.
+// One problem: workgroup x = right-hand-side column.  A zero diagonal entry
+// sets ctrl[6] = max(N - j) and ctrl[7] = N.
 template <int NB>
-__global__ __launch_bounds__(NB) void trsm_batched_kernel(const ProbDesc* descs, char* w, int32_t* ctrl,
-                                                          int32_t* info) {
+__global__ __launch_bounds__(256) void trsv_kernel(const double* R, double* Y, int cw, int mt, int64_t N,
+                                                   int32_t* ctrl) {
+  trsv_column<NB>(R, Y, cw, mt, N, blockIdx.x, ctrl, &ctrl[6], &ctrl[7]);
+}
+
+// Every problem of a batch in one launch: workgroup (x, q) solves
+// right-hand-side column x of problem q (its B tile columns follow the
+// matrix tiles).
+template <int NB>
+__global__ __launch_bounds__(256) void trsv_batched_kernel(const ProbDesc* descs, char* w, int32_t* ctrl,
+                                                           int32_t* info) {
   const ProbDesc* d = descs + blockIdx.y;
-  const int nrhs = d->nrhs;
-  if (nrhs == 0) return;
-  const int nbc = (nrhs + 63) / 64, groups = nbc > 1 ? 4 : (nrhs + 15) / 16;
-  if ((int)blockIdx.x >= nbc * groups) return;
+  if ((int)blockIdx.x >= d->nrhs) return;
   const double* R = (const double*)(w + d->tiles);
   double* Y = (double*)(w + d->tiles) + (int64_t)d->mt * d->nt * NB * NB;
-  for (int i = d->nt - 1; i >= 0; --i) {
-    trsm_tile_row<double, NB>(R, Y, NB / 64, ctrl, info + blockIdx.y, nullptr, d->N, d->mt, d->nt, i,
-                              (int)blockIdx.x / groups, (int)blockIdx.x % groups);
-    __syncthreads();  // the rows of x just stored are read by the next tile rows
-  }
+  trsv_column<NB>(R, Y, NB, d->mt, d->N, blockIdx.x, ctrl, info + blockIdx.y, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1631,39 +1613,16 @@ int launch_tile_copy(double* A, int64_t lda, double* At, int64_t M, int64_t N, i
   return launch_tile_copy(A, 0, lda, At, 0, M, N, nb, tw, mt, nt, in, stream);
 }
 
-template <typename E>
-static int launch_trsm_t(int nb, const E* R, E* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
-                         int groups, void* stream) {
-  for (int i = nt - 1; i >= 0; --i) {
-    const dim3 grid(nbc * groups), block(nb);
-    const size_t lds = (size_t)nb * 17 * sizeof(E);
-    switch (nb) {
-      case 64:
-        hipLaunchKernelGGL((trsm_tile_row_kernel<E, 64>), grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N,
-                           mt, nt, i, groups);
-        break;
-      case 128:
-        hipLaunchKernelGGL((trsm_tile_row_kernel<E, 128>), grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N,
-                           mt, nt, i, groups);
-        break;
-      default:
-        hipLaunchKernelGGL((trsm_tile_row_kernel<E, 256>), grid, block, lds, (hipStream_t)stream, R, Y, cpt, ctrl, N,
-                           mt, nt, i, groups);
-        break;
-    }
-    if (int rc = record_hip(hipGetLastError(), "trsm_tile_row_kernel launch")) return rc;
+int launch_trsv(int nb, const double* R, double* Y, int cw, int32_t* ctrl, int64_t N, int mt, int nrhs,
+                void* stream) {
+  if (nrhs <= 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  switch (nb) {
+    case 64: hipLaunchKernelGGL(trsv_kernel<64>, dim3(nrhs), dim3(256), 0, s, R, Y, cw, mt, N, ctrl); break;
+    case 128: hipLaunchKernelGGL(trsv_kernel<128>, dim3(nrhs), dim3(256), 0, s, R, Y, cw, mt, N, ctrl); break;
+    default: hipLaunchKernelGGL(trsv_kernel<256>, dim3(nrhs), dim3(256), 0, s, R, Y, cw, mt, N, ctrl); break;
   }
-  return 0;
-}
-
-int launch_trsm(int nb, const double* R, double* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
-                int groups, void* stream) {
-  return launch_trsm_t<double>(nb, R, Y, cpt, ctrl, N, mt, nt, nbc, groups, stream);
-}
-
-int launch_trsm_f32(int nb, const float* R, float* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
-                    int groups, void* stream) {
-  return launch_trsm_t<float>(nb, R, Y, cpt, ctrl, N, mt, nt, nbc, groups, stream);
+  return record_hip(hipGetLastError(), "trsv_kernel launch");
 }
 
 int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, int64_t max_elems, void* stream) {
@@ -1677,18 +1636,17 @@ int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, 
   return record_hip(hipGetLastError(), "copy_batched_kernel launch");
 }
 
-int launch_trsm_batched(int nb, const ProbDesc* d, char* w, int32_t* ctrl, int32_t* info, int count, int gmax,
+int launch_trsv_batched(int nb, const ProbDesc* d, char* w, int32_t* ctrl, int32_t* info, int count, int max_nrhs,
                         void* stream) {
-  if (count <= 0 || gmax <= 0) return 0;
-  const dim3 grid(gmax, count), block(nb);
-  const size_t lds = (size_t)nb * 17 * sizeof(double);
+  if (count <= 0 || max_nrhs <= 0) return 0;
+  const dim3 grid(max_nrhs, count), block(256);
   hipStream_t s = (hipStream_t)stream;
   switch (nb) {
-    case 64: hipLaunchKernelGGL(trsm_batched_kernel<64>, grid, block, lds, s, d, w, ctrl, info); break;
-    case 128: hipLaunchKernelGGL(trsm_batched_kernel<128>, grid, block, lds, s, d, w, ctrl, info); break;
-    default: hipLaunchKernelGGL(trsm_batched_kernel<256>, grid, block, lds, s, d, w, ctrl, info); break;
+    case 64: hipLaunchKernelGGL(trsv_batched_kernel<64>, grid, block, 0, s, d, w, ctrl, info); break;
+    case 128: hipLaunchKernelGGL(trsv_batched_kernel<128>, grid, block, 0, s, d, w, ctrl, info); break;
+    default: hipLaunchKernelGGL(trsv_batched_kernel<256>, grid, block, 0, s, d, w, ctrl, info); break;
   }
-  return record_hip(hipGetLastError(), "trsm_batched_kernel launch");
+  return record_hip(hipGetLastError(), "trsv_batched_kernel launch");
 }
 
 template <typename E, int NB>

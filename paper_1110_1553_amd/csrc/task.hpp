@@ -75,13 +75,11 @@ int launch_tile_copy(void* A, int a_f32, int64_t lda, void* At, int at_f32, int6
                      int mt, int nt, bool in, void* stream);
 
 // Back substitution with the leading N x N triangle of the factored tiles R
-// on the first N rows of Y (tile columns of nb rows x 64 cpt columns; nbc
-// blocks of 64 columns, `groups` groups of 16 columns per block solved),
-// tile row by tile row.
-int launch_trsm(int nb, const double* R, double* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
-                int groups, void* stream);
-int launch_trsm_f32(int nb, const float* R, float* Y, int cpt, int32_t* ctrl, int64_t N, int mt, int nt, int nbc,
-                    int groups, void* stream);
+// on the first N rows of the nrhs columns of Y (blocks of nb rows x cw
+// columns: cw = nb for the tile columns of B in a factorization workspace,
+// 64 for the blocks of the apply path), one workgroup per column.
+int launch_trsv(int nb, const double* R, double* Y, int cw, int32_t* ctrl, int64_t N, int mt, int nrhs,
+                void* stream);
 
 // Stores "where: message" of a failed HIP call for hqr_last_error(); returns
 // HQR_ERR_HIP on failure, 0 on success.
@@ -96,7 +94,7 @@ const char* last_error();
 // max_elems: padded elements (matrix and right-hand sides) of the largest
 // problem, which sizes the copy grid.
 int launch_copy_batched(const ProbDesc* d, char* w, int count, int nb, bool in, int64_t max_elems, void* stream);
-int launch_trsm_batched(int nb, const ProbDesc* d, char* w, int32_t* ctrl, int32_t* info, int count, int gmax,
+int launch_trsv_batched(int nb, const ProbDesc* d, char* w, int32_t* ctrl, int32_t* info, int count, int max_nrhs,
                         void* stream);
 
 // Least-squares refinement steps (FP64 vectors; R as float tiles of nb,
