@@ -855,28 +855,45 @@ __device__ __forceinline__ void panel_left_update_4w(E* A, E* R, const E* T, int
 // ---------------------------------------------------------------------------
 // Scheduler steps.
 
-// Waits until *c >= v.  Returns false when the launch has been aborted: by
-// this wait running past the spin limit (it then records the abort and what
-// it was waiting for in ctrl[1..5]) or by another workgroup's abort.
-__device__ __forceinline__ bool wait_counter(int32_t* c, uint32_t v, const LaunchArgs& a, int64_t& spins, int t) {
-  if (v == 0) return true;
+// Waits until every lane's counter *c >= v (one counter per lane of the
+// calling wave).  Returns false when the launch has been aborted: by this
+// wait running past the spin limit (it then records the abort and what it
+// was waiting for in ctrl[1..5]) or by another workgroup's abort.
+// Every lane of the wave calls it; a lane with c == null or v == 0 has
+// nothing to wait for.  The counters are polled in parallel instead of one
+// after another.  Returns the same (uniform) result in every lane; on a
+// time-out the lowest lane still waiting records its counter.
+__device__ __forceinline__ bool wait_lanes(int32_t* c, uint32_t v, const LaunchArgs& a, int t) {
+  bool done = (c == nullptr) || (v == 0);
+  int64_t spins = 0;
+  const int lane = threadIdx.x & 63;
   for (;;) {
-    const uint32_t seen = (uint32_t)__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (seen >= v) return true;
+    uint32_t seen = 0;
+    if (!done) {
+      seen = (uint32_t)__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      done = seen >= v;
+    }
+    const uint64_t pending = __ballot(!done);
+    if (pending == 0) return true;
     ++spins;
     if (spins > a.spin_limit) {
-      int32_t none = 0;
-      if (__hip_atomic_compare_exchange_strong(&a.ctrl[1], &none, (int32_t)HQR_ERR_WATCHDOG, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        __hip_atomic_store(&a.ctrl[2], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.ctrl[3], (int32_t)(c - a.cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.ctrl[4], (int32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.ctrl[5], (int32_t)seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == __ffsll((unsigned long long)pending) - 1) {
+        int32_t none = 0;
+        if (__hip_atomic_compare_exchange_strong(&a.ctrl[1], &none, (int32_t)HQR_ERR_WATCHDOG, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          __hip_atomic_store(&a.ctrl[2], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&a.ctrl[3], (int32_t)(c - a.cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&a.ctrl[4], (int32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&a.ctrl[5], (int32_t)seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
       return false;
     }
-    if ((spins & 63) == 0 && __hip_atomic_load(&a.ctrl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-      return false;
+    if ((spins & 63) == 0) {
+      const int st = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(&a.ctrl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (st != 0) return false;
+    }
     __builtin_amdgcn_s_sleep(2);
   }
 }
@@ -950,41 +967,48 @@ __device__ __noinline__ int take_task(const LaunchArgs& a) {
 template <typename E, int NB>
 __device__ __noinline__ int wait_task(const LaunchArgs& a, int t, const DevTask& task) {
   Smem<E, NB>& sm = smem<E, NB>();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    // lane l waits for the l-th (counter, version) pair of the task
+    const int l = threadIdx.x;
     const int op = task.op, i = task.row, piv = task.killer, k = task.k, j = task.j;
-    int64_t spins = 0;
-    bool ok = true;
+    int32_t* c = nullptr;
+    uint32_t v = 0;
     if (a.B) {
       // apply launch: one counter per block of B
-      ok = (op == UNMQR) ? wait_counter(counter(a, i, j, 0), task.v[1], a, spins, t)
-                         : wait_counter(counter(a, piv, j, 0), task.v[1], a, spins, t) &&
-                               wait_counter(counter(a, i, j, 0), task.v[2], a, spins, t);
+      if (op == UNMQR) {
+        if (l == 0) c = counter(a, i, j, 0), v = task.v[1];
+      } else {
+        if (l == 0) c = counter(a, piv, j, 0), v = task.v[1];
+        if (l == 1) c = counter(a, i, j, 0), v = task.v[2];
+      }
     } else {
       const int c0 = task.chunk, cn = task.pad >> 8, cv = task.pad & 0xff;
       switch (op) {
         case GEQRT:
-          ok = wait_counter(counter(a, i, k, 0), task.v[0], a, spins, t);
+          if (l == 0) c = counter(a, i, k, 0), v = task.v[0];
           break;
         case TSQRT:
         case TTQRT:
-          ok = wait_counter(counter(a, piv, k, 0), task.v[0], a, spins, t) &&
-               wait_counter(counter(a, i, k, 0), task.v[1], a, spins, t);
+          if (l == 0) c = counter(a, piv, k, 0), v = task.v[0];
+          if (l == 1) c = counter(a, i, k, 0), v = task.v[1];
           break;
         case UNMQR:
-          ok = wait_counter(counter(a, i, k, cv), task.v[0], a, spins, t);
-          for (int c = c0; c < c0 + cn && ok; ++c) ok = wait_counter(counter(a, i, j, c), task.v[1], a, spins, t);
+          if (l == 0) c = counter(a, i, k, cv), v = task.v[0];
+          if (l >= 1 && l <= cn) c = counter(a, i, j, c0 + l - 1), v = task.v[1];
           break;
         default:
-          ok = wait_counter(counter(a, i, k, cv), task.v[0], a, spins, t);
-          for (int c = c0; c < c0 + cn && ok; ++c)
-            ok = wait_counter(counter(a, piv, j, c), task.v[1], a, spins, t) &&
-                 wait_counter(counter(a, i, j, c), task.v[2], a, spins, t);
+          if (l == 0) c = counter(a, i, k, cv), v = task.v[0];
+          if (l >= 1 && l <= cn) c = counter(a, piv, j, c0 + l - 1), v = task.v[1];
+          if (l > cn && l <= 2 * cn) c = counter(a, i, j, c0 + l - cn - 1), v = task.v[2];
           break;
       }
     }
-    sm.ok = ok ? 1 : 0;
-    trace(a, t, ok ? TR_READY : TR_ABORT);
-    stamp(a, t, 1);
+    const bool ok = wait_lanes(c, v, a, t);
+    if (l == 0) {
+      sm.ok = ok ? 1 : 0;
+      trace(a, t, ok ? TR_READY : TR_ABORT);
+      stamp(a, t, 1);
+    }
   }
   __syncthreads();
   const int ok = __builtin_amdgcn_readfirstlane(sm.ok);
@@ -999,15 +1023,18 @@ template <typename E, int NB>
 __device__ __noinline__ int wait_block(const LaunchArgs& a, int t, const DevTask& task, int b) {
   Smem<E, NB>& sm = smem<E, NB>();
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t spins = 0;
-    bool ok = true;
-    if (task.op == GEQRT)
-      ok = wait_counter(counter(a, task.row, task.k, b), task.v[0], a, spins, t);
-    else
-      ok = wait_counter(counter(a, task.killer, task.k, b), task.v[0], a, spins, t) &&
-           wait_counter(counter(a, task.row, task.k, b), task.v[1], a, spins, t);
-    sm.ok = ok ? 1 : 0;
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    int32_t* c = nullptr;
+    uint32_t v = 0;
+    if (task.op == GEQRT) {
+      if (l == 0) c = counter(a, task.row, task.k, b), v = task.v[0];
+    } else {
+      if (l == 0) c = counter(a, task.killer, task.k, b), v = task.v[0];
+      if (l == 1) c = counter(a, task.row, task.k, b), v = task.v[1];
+    }
+    const bool ok = wait_lanes(c, v, a, t);
+    if (l == 0) sm.ok = ok ? 1 : 0;
   }
   __syncthreads();
   const int ok = __builtin_amdgcn_readfirstlane(sm.ok);
