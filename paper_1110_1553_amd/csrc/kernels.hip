@@ -203,6 +203,7 @@ struct Smem {
   E tau[IB];
   V4<E> xw[8 * 64];  // partial W = V^T C of each wave (row-split panel updates)
   int task;  // index of the task taken by the workgroup (-1: launch aborted)
+  int next;  // the following task index, taken ahead by finish_task (-2: none)
   int ok;    // 1 if the task's dependencies were met, 0 if the launch was aborted
 };
 
@@ -938,10 +939,13 @@ template <typename E, int NB>
 __device__ __noinline__ int take_task(const LaunchArgs& a) {
   Smem<E, NB>& sm = smem<E, NB>();
   if (threadIdx.x == 0) {
-    int t = -1;
+    int t = sm.next;
+    sm.next = -2;
     // an aborted launch hands out no more tasks: every workgroup leaves at
     // its next pick, so the kernel ends soon after the first time-out
-    if (__hip_atomic_load(&a.ctrl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    if (__hip_atomic_load(&a.ctrl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      t = -1;
+    else if (t == -2)
       t = __hip_atomic_fetch_add(&a.ctrl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (t >= a.ntasks) t = -1;
     sm.task = t;
@@ -1059,9 +1063,13 @@ __device__ __noinline__ void release_block(const LaunchArgs& a, const DevTask& t
 // release_block).
 template <typename E, int NB>
 __device__ __noinline__ void finish_task(const LaunchArgs& a, int t, const DevTask& task) {
+  // the next task index is taken while this task's stores drain
+  int next = -2;
+  if (threadIdx.x == 0) next = __hip_atomic_fetch_add(&a.ctrl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   stores_done();
   __syncthreads();
   if (threadIdx.x == 0) {
+    smem<E, NB>().next = next;
     trace(a, t, TR_DONE);
     stamp(a, t, 2);
     const int op = task.op, i = task.row, piv = task.killer, k = task.k, j = task.j;
@@ -1201,6 +1209,7 @@ __device__ __forceinline__ void bind_problem(LaunchArgs& la, const LaunchArgs& a
 template <typename E, int NB, bool BATCH>
 __global__ __launch_bounds__(NT, 1) void persistent_kernel(LaunchArgs args) {
   LaunchArgs la = args;
+  if (threadIdx.x == 0) smem<E, NB>().next = -2;
   for (;;) {
     const int t = take_task<E, NB>(args);
     if (t < 0) break;
