@@ -136,6 +136,19 @@ __device__ __forceinline__ f2 bload2<float>(__amdgpu_buffer_rsrc_t r, int off) {
 __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, int off, d2 v) {
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off * 8, 0, kCoherent);
 }
+// One element at byte offset voff + soff (soff a wave-uniform constant),
+// plain (non-coherent) load: for kernels that read what an earlier launch
+// wrote.
+template <typename E>
+__device__ __forceinline__ E bload1(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ double bload1<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float bload1<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
 template <typename E>
 __device__ __forceinline__ V4<E> ld4(__amdgpu_buffer_rsrc_t r, int off);
 template <>
@@ -1304,74 +1317,141 @@ __global__ void copy_batched_kernel(const ProbDesc* descs, char* w, int nb, int 
 }
 
 // ---------------------------------------------------------------------------
-// Back substitution R x = y with the leading N x N triangle of the factored
-// tiles R (tile (i, j) at (j mt + i) NB^2, column-major, leading dimension
-// NB), one right-hand-side column c per workgroup of 256 threads.  y is
-// column c of a blocked matrix with cw columns per block (block (i, jb) at
-// Y + (jb mt + i) NB cw, column-major with leading dimension NB): the tile
-// columns of B appended to the factorization (cw = NB) or the blocks of B
-// of the apply path (cw = 64).  x overwrites y in rows 0 .. N-1.
-// Unknowns are taken 64 at a time from the bottom: the 64 x 64 diagonal
-// triangle is staged in LDS and solved by one wave (lane = unknown, one
-// shuffle per step), then all threads remove the block from the rows above
-// it.  A zero diagonal entry R_jj is recorded in ctrl (status
-// HQR_ERR_SINGULAR, *info = max over such j of N - j; nword, when not null,
-// receives N).
-template <int NB>
-__device__ void trsv_column(const double* R, double* Y, int cw, int mt, int64_t N, int c, int32_t* ctrl,
-                            int32_t* info, int32_t* nword) {
+// Triangular solves with the leading N x N upper triangle R of factored tiles
+// (tile (i, j) at (j mt + i) NB^2, column-major inside, leading dimension
+// NB; element type E, arithmetic in FP64), one right-hand side per
+// workgroup of 256 threads, y overwritten by the solution:
+//   TRANS = 0: R x = y (back substitution),  TRANS = 1: R^T x = y (forward).
+// Row a of y is at y[(a / NB) rs + a % NB]: rs = NB for a contiguous vector,
+// NB cw for a column of a matrix kept in tile-row blocks of cw columns.
+// Unknowns are taken 64 at a time (from the bottom for TRANS = 0): wave 0
+// holds the block's 64 x 64 triangle in registers, one equation per lane,
+// and solves it lane by lane (reciprocals of the diagonal taken in
+// parallel, each new unknown broadcast with a lane read); then every thread
+// removes the block from one of the rows still to be solved at a time,
+// with all 64 products' loads issued together.  With ctrl not null a zero
+// diagonal entry R_jj is recorded there (status HQR_ERR_SINGULAR, *info =
+// max over such j of N - j; nword, when not null, receives N).
+template <typename E, int NB, int TRANS>
+__device__ void trsv_solve(const E* R, int mt, int64_t N, double* y, int64_t rs, int32_t* ctrl, int32_t* info,
+                           int32_t* nword) {
   __shared__ double xb[64];
-  __shared__ double Rd[64 * 65];  // Rd[i * 65 + j] = R(k0 + i, k0 + j)
-  double* y = Y + (int64_t)(c / cw) * mt * NB * cw + (int64_t)(c % cw) * NB;
-  const int64_t rs = (int64_t)NB * cw;  // from one tile row of y to the next
-  const int64_t tsz = (int64_t)NB * NB;
+  __shared__ double Rd[64 * 65];  // Rd[i * 65 + j] = R(k0 + i, k0 + j), zero outside the triangle
   const int t = threadIdx.x, lane = t & 63;
+  const int64_t tsz = (int64_t)NB * NB;
   const int64_t nblk = (N + 63) / 64;
-  for (int64_t bi = nblk - 1; bi >= 0; --bi) {
-    const int64_t k0 = bi * 64;
+  for (int64_t bi = 0; bi < nblk; ++bi) {
+    const int64_t blk = TRANS ? bi : nblk - 1 - bi;
+    const int64_t k0 = blk * 64;
     const int nv = (int)((N - k0) < 64 ? (N - k0) : 64);
     const int64_t kt = k0 / NB, ko = k0 - kt * NB;  // the 64 rows / columns lie in tile row / column kt
-    const double* Rkk = R + (kt * mt + kt) * tsz + ko + ko * NB;
-    for (int e = t; e < 64 * 64; e += 256) {
-      const int i = e & 63, j = e >> 6;
-      Rd[i * 65 + j] = (i < nv && j < nv && i <= j) ? Rkk[i + (int64_t)j * NB] : 0.0;
+    const E* Rkk = R + (kt * mt + kt) * tsz + ko + ko * NB;
+    {
+      // the whole 64 x 64 square lies inside tile (kt, kt): every load is
+      // issued before the first is used
+      E rv[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int e = t + 256 * k, i = e & 63, j = e >> 6;
+        rv[k] = Rkk[i + (int64_t)j * NB];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int e = t + 256 * k, i = e & 63, j = e >> 6;
+        Rd[i * 65 + j] = (i < nv && j < nv && i <= j) ? (double)rv[k] : 0.0;
+      }
     }
     double* yk = y + kt * rs + ko;  // y(k0)
     __syncthreads();
     if (t < 64) {
-      double v = lane < nv ? yk[lane] : 0.0;
-      for (int s = nv - 1; s >= 0; --s) {
-        const double dg = Rd[s * 65 + s];
-        if (dg == 0.0 && lane == s) {
-          int32_t none = 0;
-          __hip_atomic_compare_exchange_strong(&ctrl[1], &none, (int32_t)HQR_ERR_SINGULAR, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_fetch_max(info, (int32_t)(N - (k0 + s)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (nword) __hip_atomic_store(nword, (int32_t)N, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        const double xs = __shfl(v, s) / dg;
-        if (lane == s) v = xs;
-        if (lane < s) v -= Rd[lane * 65 + s] * xs;
+      // cf[s]: coefficient of unknown k0 + s in this lane's equation; a lane
+      // beyond the nv unknowns solves 1 x = 0 and touches no other lane
+      double cf[64];
+#pragma unroll
+      for (int s = 0; s < 64; ++s) cf[s] = TRANS ? Rd[s * 65 + lane] : Rd[lane * 65 + s];
+      const bool in = lane < nv;
+      const double dg = in ? Rd[lane * 66] : 1.0;
+      if (ctrl && in && dg == 0.0) {
+        int32_t none = 0;
+        __hip_atomic_compare_exchange_strong(&ctrl[1], &none, (int32_t)HQR_ERR_SINGULAR, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_max(info, (int32_t)(N - (k0 + lane)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (nword) __hip_atomic_store(nword, (int32_t)N, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      xb[lane] = v;
+      const double rinv = 1.0 / dg;
+      double v = in ? yk[lane] : 0.0;
+#pragma unroll
+      for (int st = 0; st < 64; ++st) {
+        const int s = TRANS ? st : 63 - st;
+        const double xs = readlane(v * rinv, s);
+        // lanes whose unknown is still open take the product; solved lanes keep theirs
+        const double u = v - cf[s] * xs;
+        v = (lane == s) ? xs : ((TRANS ? lane > s : lane < s) ? u : v);
+      }
+      xb[lane] = lane < nv ? v : 0.0;
       if (lane < nv) yk[lane] = v;
     }
     __syncthreads();
-    // rows above the block: y(a) -= sum_s R(a, k0 + s) x_s
-    for (int64_t a = t; a < k0; a += 256) {
+    // rows still open: TRANS those after the block (R(k0 + c, a), contiguous
+    // in c: 16-byte loads), else those before it (R(a, k0 + c), stride NB in
+    // c).  The 64 rows of a wave lie in one tile row (lo and the wave's first
+    // row are multiples of 64), so the tile is addressed through a buffer
+    // resource with one lane offset and a constant offset per column.  Only
+    // the bottom block of TRANS = 0 can hold fewer than 64 unknowns.
+    const int64_t lo = TRANS ? k0 + 64 : 0, hi = TRANS ? N : k0;
+    for (int64_t a = lo + t; a < hi; a += 256) {
       const int64_t at = a / NB, ao = a - at * NB;
-      const double* ra = R + (kt * mt + at) * tsz + ao + ko * NB;  // R(a, k0)
-      double acc0 = 0.0, acc1 = 0.0;
-      int s = 0;
-      for (; s + 1 < nv; s += 2) {
-        acc0 += ra[(int64_t)s * NB] * xb[s];
-        acc1 += ra[(int64_t)(s + 1) * NB] * xb[s + 1];
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      if (TRANS) {
+        const __amdgpu_buffer_rsrc_t rr = rsrc(R + (at * mt + kt) * tsz);  // tile (kt, at)
+        const int vo = (int)((ko + ao * NB) * (int64_t)sizeof(E));
+        constexpr int PER = 16 / (int)sizeof(E);  // elements per 16-byte load
+        u4 raw[64 / PER];
+#pragma unroll
+        for (int q = 0; q < 64 / PER; ++q) raw[q] = __builtin_amdgcn_raw_buffer_load_b128(rr, vo + 16 * q, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 64 / PER; ++q) {
+          if constexpr (sizeof(E) == 8) {
+            const d2 x = __builtin_bit_cast(d2, raw[q]);
+            acc[(2 * q) & 3] += x.x * xb[2 * q];
+            acc[(2 * q + 1) & 3] += x.y * xb[2 * q + 1];
+          } else {
+            const f4 x = __builtin_bit_cast(f4, raw[q]);
+            acc[0] += (double)x.x * xb[4 * q];
+            acc[1] += (double)x.y * xb[4 * q + 1];
+            acc[2] += (double)x.z * xb[4 * q + 2];
+            acc[3] += (double)x.w * xb[4 * q + 3];
+          }
+        }
+      } else {
+        const __amdgpu_buffer_rsrc_t rr = rsrc(R + (kt * mt + at) * tsz);  // tile (at, kt)
+        const int vo = (int)((ao + ko * NB) * (int64_t)sizeof(E));
+        constexpr int CS = NB * (int)sizeof(E);  // bytes from one column to the next
+        if (nv == 64) {
+          E r0[64];
+#pragma unroll
+          for (int c = 0; c < 64; ++c) r0[c] = bload1<E>(rr, vo, c * CS);
+#pragma unroll
+          for (int c = 0; c < 64; ++c) acc[c & 3] += (double)r0[c] * xb[c];
+        } else {
+          for (int c = 0; c < nv; ++c) acc[c & 3] += (double)bload1<E>(rr, vo, c * CS) * xb[c];
+        }
       }
-      if (s < nv) acc0 += ra[(int64_t)s * NB] * xb[s];
-      y[at * rs + ao] -= acc0 + acc1;
+      y[at * rs + ao] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
     __syncthreads();
   }
+}
+
+// R x = y for column c of a matrix Y kept in tile-row blocks of cw columns
+// (block (i, jb) at Y + (jb mt + i) NB cw, column-major with leading
+// dimension NB): the tile columns of B appended to the factorization
+// (cw = NB) or the blocks of B of the apply path (cw = 64).
+template <int NB>
+__device__ __forceinline__ void trsv_column(const double* R, double* Y, int cw, int mt, int64_t N, int c,
+                                            int32_t* ctrl, int32_t* info, int32_t* nword) {
+  double* y = Y + (int64_t)(c / cw) * mt * NB * cw + (int64_t)(c % cw) * NB;
+  trsv_solve<double, NB, 0>(R, mt, N, y, (int64_t)NB * cw, ctrl, info, nword);
 }
 
 // One problem: workgroup x = right-hand-side column.  A zero diagonal entry
@@ -1400,7 +1480,7 @@ __global__ __launch_bounds__(256) void trsv_batched_kernel(const ProbDesc* descs
 
 // f = b - r - A x (r may be null).  A: M x N column-major (lda).  Workgroup
 // of 256 threads = 64 rows x 4 column groups (each group sums every fourth
-// column), partial sums combined in a fixed order.
+// column, eight loads in flight), partial sums combined in a fixed order.
 __global__ __launch_bounds__(256) void ir_residual_kernel(const double* A, int64_t lda, int64_t M, int64_t N,
                                                           const double* x, const double* b, const double* r,
                                                           double* f) {
@@ -1408,8 +1488,10 @@ __global__ __launch_bounds__(256) void ir_residual_kernel(const double* A, int64
   const int lr = threadIdx.x & 63, cg = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 64 + lr;
   double s = 0.0;
-  if (row < M)
+  if (row < M) {
+#pragma unroll 8
     for (int64_t j = cg; j < N; j += 4) s += A[row + j * lda] * x[j];
+  }
   part[cg][lr] = s;
   __syncthreads();
   if (cg == 0 && row < M)
@@ -1417,99 +1499,50 @@ __global__ __launch_bounds__(256) void ir_residual_kernel(const double* A, int64
 }
 
 // g = -A^T r (SQ = 0), or g_j = sum_i A_ij^2 (SQ = 1, r unused).
-// Workgroup per 8 columns; 256 threads stride over the rows; a fixed
-// reduction tree per column.
+// Workgroup per IR_ATR_COLS columns (so that a launch has several
+// workgroups per compute unit); 256 threads stride over the rows, four rows
+// in flight each; a fixed reduction tree per column.
+constexpr int IR_ATR_COLS = 2;
 template <int SQ>
 __global__ __launch_bounds__(256) void ir_atr_kernel(const double* A, int64_t lda, int64_t M, int64_t N,
                                                      const double* r, double* g) {
-  __shared__ double part[8][257];
+  constexpr int C = IR_ATR_COLS;
+  __shared__ double part[C][257];
   const int t = threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.x * 8;
-  const int nc = (int)((N - c0) < 8 ? (N - c0) : 8);
-  double s[8];
+  const int64_t c0 = (int64_t)blockIdx.x * C;
+  const int nc = (int)((N - c0) < C ? (N - c0) : C);
+  double s[C];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) s[c] = 0.0;
+  for (int c = 0; c < C; ++c) s[c] = 0.0;
+#pragma unroll 4
   for (int64_t i = t; i < M; i += 256) {
     const double ri = SQ ? 0.0 : r[i];
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
+    for (int c = 0; c < C; ++c)
       if (c < nc) {
         const double aij = A[i + (c0 + c) * lda];
         s[c] += aij * (SQ ? aij : ri);
       }
   }
 #pragma unroll
-  for (int c = 0; c < 8; ++c) part[c][t] = s[c];
+  for (int c = 0; c < C; ++c) part[c][t] = s[c];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (t < w) {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) part[c][t] += part[c][t + w];
+      for (int c = 0; c < C; ++c) part[c][t] += part[c][t + w];
     }
     __syncthreads();
   }
   if (t < nc) g[c0 + t] = SQ ? part[t][0] : -part[t][0];
 }
 
-// Triangular solves with the leading N x N triangle R of float tiles (tile
-// (i, j) at (j mt + i) nb^2, column-major inside), in FP64 arithmetic, one
-// workgroup of 256 threads, y overwritten by the solution:
-//   TRANS = 0: R x = y (backward);  TRANS = 1: R^T x = y (forward).
-// Blocks of 64 unknowns: wave 0 solves the block's 64 x 64 triangle lane
-// by lane (lane l holds unknown k0 + l), then all threads remove the block
-// from the remaining right-hand side.
-template <int TRANS>
-__global__ __launch_bounds__(256) void ir_trsv_kernel(const float* R, int nb, int mt, int64_t N, double* y) {
-  __shared__ double xb[64];
-  __shared__ float Rd[64 * 65];  // the block's diagonal triangle: Rd[i * 65 + j] = R(k0 + i, k0 + j)
-  const int t = threadIdx.x, lane = t & 63;
-  const int64_t nblk = (N + 63) / 64;
-  const int64_t tsz = (int64_t)nb * nb;
-  for (int64_t bi = 0; bi < nblk; ++bi) {
-    const int64_t blk = TRANS ? bi : nblk - 1 - bi;
-    const int64_t k0 = blk * 64;
-    const int nv = (int)((N - k0) < 64 ? (N - k0) : 64);
-    // the 64 rows / columns k0.. lie inside tile row / column kt (nb is a multiple of 64)
-    const int64_t kt = k0 / nb, ko = k0 - kt * nb;
-    const float* Rkk = R + (kt * mt + kt) * tsz + ko + ko * nb;  // R(k0, k0)
-    for (int e = t; e < 64 * 64; e += 256) {
-      const int i = e & 63, j = e >> 6;
-      Rd[i * 65 + j] = (i < nv && j < nv && i <= j) ? Rkk[i + (int64_t)j * nb] : 0.0f;
-    }
-    __syncthreads();
-    if (t < 64) {
-      double v = lane < nv ? y[k0 + lane] : 0.0;
-      for (int s = 0; s < nv; ++s) {
-        const int c = TRANS ? s : nv - 1 - s;
-        const double xc = __shfl(v, c) / (double)Rd[c * 65 + c];
-        if (lane == c) v = xc;
-        // TRANS: lanes after c take R(k0+c, k0+lane) x_c; else lanes before c take R(k0+lane, k0+c) x_c
-        if (TRANS ? (lane > c && lane < nv) : (lane < c))
-          v -= (double)(TRANS ? Rd[c * 65 + lane] : Rd[lane * 65 + c]) * xc;
-      }
-      xb[lane] = v;
-      if (lane < nv) y[k0 + lane] = v;
-    }
-    __syncthreads();
-    // the rest of the right-hand side: TRANS rows after the block (R(k0 + c, a),
-    // contiguous in c), else rows before it (R(a, k0 + c), stride nb in c)
-    const int64_t lo = TRANS ? k0 + nv : 0, hi = TRANS ? N : k0;
-    for (int64_t a = lo + t; a < hi; a += 256) {
-      const int64_t at = a / nb, ao = a - at * nb;
-      const float* p = TRANS ? R + (at * mt + kt) * tsz + ko + ao * nb   // R(k0, a)
-                             : R + (kt * mt + at) * tsz + ao + ko * nb;  // R(a, k0)
-      const int64_t step = TRANS ? 1 : nb;
-      double acc0 = 0.0, acc1 = 0.0;
-      int c = 0;
-      for (; c + 1 < nv; c += 2) {
-        acc0 += (double)p[c * step] * xb[c];
-        acc1 += (double)p[(c + 1) * step] * xb[c + 1];
-      }
-      if (c < nv) acc0 += (double)p[c * step] * xb[c];
-      y[a] -= acc0 + acc1;
-    }
-    __syncthreads();
-  }
+// Triangular solves of the refinement with the float tiles R of the FP32
+// factorization, in FP64 arithmetic, y (contiguous) overwritten:
+//   TRANS = 0: R x = y,  TRANS = 1: R^T x = y.
+template <int NB, int TRANS>
+__global__ __launch_bounds__(256) void ir_trsv_kernel(const float* R, int mt, int64_t N, double* y) {
+  trsv_solve<float, NB, TRANS>(R, mt, N, y, NB, nullptr, nullptr, nullptr);
 }
 
 // y = d(0:N) - h;  then d(0:N) = h  (the two uses of h in one correction).
@@ -1582,19 +1615,27 @@ int launch_ir_residual(const double* A, int64_t lda, int64_t M, int64_t N, const
 
 int launch_ir_atr(const double* A, int64_t lda, int64_t M, int64_t N, const double* r, double* g, void* stream) {
   if (r)
-    hipLaunchKernelGGL(ir_atr_kernel<0>, dim3((unsigned)((N + 7) / 8)), dim3(256), 0, (hipStream_t)stream, A, lda, M,
-                       N, r, g);
+    hipLaunchKernelGGL(ir_atr_kernel<0>, dim3((unsigned)((N + IR_ATR_COLS - 1) / IR_ATR_COLS)), dim3(256), 0,
+                       (hipStream_t)stream, A, lda, M, N, r, g);
   else
-    hipLaunchKernelGGL(ir_atr_kernel<1>, dim3((unsigned)((N + 7) / 8)), dim3(256), 0, (hipStream_t)stream, A, lda, M,
-                       N, r, g);
+    hipLaunchKernelGGL(ir_atr_kernel<1>, dim3((unsigned)((N + IR_ATR_COLS - 1) / IR_ATR_COLS)), dim3(256), 0,
+                       (hipStream_t)stream, A, lda, M, N, r, g);
   return record_hip(hipGetLastError(), "ir_atr_kernel launch");
 }
 
 int launch_ir_trsv(const float* R, int nb, int mt, int64_t N, double* y, bool trans, void* stream) {
-  if (trans)
-    hipLaunchKernelGGL(ir_trsv_kernel<1>, dim3(1), dim3(256), 0, (hipStream_t)stream, R, nb, mt, N, y);
-  else
-    hipLaunchKernelGGL(ir_trsv_kernel<0>, dim3(1), dim3(256), 0, (hipStream_t)stream, R, nb, mt, N, y);
+  hipStream_t s = (hipStream_t)stream;
+#define HQR_IR_TRSV(NBV)                                                                        \
+  if (trans)                                                                                    \
+    hipLaunchKernelGGL((ir_trsv_kernel<NBV, 1>), dim3(1), dim3(256), 0, s, R, mt, N, y);        \
+  else                                                                                          \
+    hipLaunchKernelGGL((ir_trsv_kernel<NBV, 0>), dim3(1), dim3(256), 0, s, R, mt, N, y);
+  switch (nb) {
+    case 64: HQR_IR_TRSV(64) break;
+    case 128: HQR_IR_TRSV(128) break;
+    default: HQR_IR_TRSV(256) break;
+  }
+#undef HQR_IR_TRSV
   return record_hip(hipGetLastError(), "ir_trsv_kernel launch");
 }
 
