@@ -1130,7 +1130,8 @@ __device__ __forceinline__ E* t_block(void* T, const LaunchArgs& a, int nb, int 
 // One tile kernel per function (each gets its own register allocation).
 // Panel tasks are on the critical path of the factorization: their waves
 // run at raised priority.  The tile(s) are processed block by block (64
-// columns), left-looking: block b waits for the predecessor's block b,
+// columns) up to the last block holding matrix columns, left-looking: block
+// b waits for the predecessor's block b,
 // takes this task's earlier panels, is factored, and is published at once
 // (except the last active block, published by finish_task).  Returns 0 when
 // the launch was aborted while waiting.
@@ -1142,7 +1143,14 @@ __device__ __noinline__ int panel_task(const LaunchArgs& a, int t, const DevTask
   const int active = task.chunk;  // blocks holding matrix columns
   __builtin_amdgcn_s_setprio(2);
   for (int b = 0; b < NB / 64; ++b) {
-    if (b > 0 && b < active && !wait_block<E, NB>(a, t, task, b)) {
+    if (b >= active) {
+      // blocks beyond the last matrix column (zero padding) are not factored:
+      // their reflectors are the identity, T = 0 (what factoring the zero
+      // columns would give), and the padding stays zero
+      for (int e = threadIdx.x; e < (NB / 16 - 4 * b) * 256; e += NT) gstore(T + 4 * b * 256 + e, E(0));
+      break;
+    }
+    if (b > 0 && !wait_block<E, NB>(a, t, task, b)) {
       __builtin_amdgcn_s_setprio(0);
       return 0;
     }
