@@ -47,6 +47,7 @@ CASES = [
     ("greedyTT-nb64-ragged", 1000, 300, 5, dict(nb=64, low="greedy")),
     ("hqr-nb128-2blocks", 1536, 448, 70, dict(nb=128, p=3, a=2, low="greedy", high="fibonacci", domino=1)),
     ("hqr-nb256", 2100, 513, 3, dict(nb=256, p=2, a=2, low="greedy", high="binary", domino=1)),
+    ("narrow-nb256", 900, 37, 2, dict(nb=256, p=1, a=2, low="greedy", high="greedy")),
     ("square-binary-nb64", 320, 320, 2, dict(nb=64, low="binary")),
 ]
 

@@ -67,6 +67,8 @@ MIXES = [
      [(1500, 300, 1), (640, 128, 2), (97, 33, 1), (3000, 511, 4)]),
     ("nb128-flat", dict(nb=128, p=1, a=100, low="flat"), [(1024, 256, 1), (700, 300, 2), (300, 130, 0)]),
     ("nb256-hqr", dict(nb=256, p=2, a=1, low="greedy", high="binary", domino=0), [(2100, 513, 3), (600, 256, 1)]),
+    ("nb256-narrow", dict(nb=256, p=1, a=4, low="greedy", high="greedy"),
+     [(900, 37, 1), (1300, 150, 1), (5000, 333, 1), (256, 200, 1), (3000, 480, 2)]),
 ]
 
 

@@ -34,6 +34,7 @@ CASES = [
     ("hqr-nb128-ragged", 1536, 449, dict(nb=128, p=3, a=2, low="greedy", high="fibonacci", domino=1)),
     ("hqr-nb256", 2100, 513, dict(nb=256, p=2, a=2, low="greedy", high="binary", domino=1)),
     ("binary-nb256-square", 768, 768, dict(nb=256, low="binary")),
+    ("narrow-nb256", 900, 37, dict(nb=256, p=1, a=2, low="greedy", high="greedy")),
     ("flat-nb128-one-tile-row", 100, 100, dict(nb=128, p=1, a=1, low="flat")),
 ]
 

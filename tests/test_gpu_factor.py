@@ -96,7 +96,10 @@ def test_square(hqr_lib, cuda):
 
 
 @pytest.mark.parametrize("M,N,nb", [(1000, 300, 64), (777, 777, 128), (4000, 100, 64), (300, 1, 64),
-                                    (64, 64, 64), (65, 65, 64), (2100, 513, 256)])
+                                    (64, 64, 64), (65, 65, 64), (2100, 513, 256),
+                                    # one tile column with 1, 2 or 3 of its 64-column blocks
+                                    # holding no matrix column
+                                    (900, 37, 256), (1300, 150, 256), (700, 130, 256)])
 def test_ragged_and_edge_shapes(hqr_lib, cuda, M, N, nb):
     check_case(M, N, 6, "ragged", nb=nb, p=2, a=2, low="greedy", high="binary", domino=1)
 
