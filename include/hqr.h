@@ -369,6 +369,17 @@ int hqr_batch_run(const hqr_batch* b, void* dwork, size_t work_bytes, void* stre
 int hqr_batch_status(const hqr_batch* b, const void* dwork, void* stream, double timeout_s, int32_t* status,
                      int32_t* first_zero);
 
+/* The same report without a host wait or a device-to-host copy, for a
+ * serving loop that polls many batches: enqueues on `stream`, after the
+ * batch's work, one single-workgroup kernel that writes host[0] = status
+ * and host[1 + q] = first zero diagonal index of problem q (or -1) for the
+ * b->count problems.  host: count + 1 int32 of pinned host memory
+ * (hipHostMalloc), which the kernel addresses directly; the values are
+ * valid once that work has completed (an event recorded after it), and stay
+ * until the next call with the same buffer.  Errors: -1 b NULL, -2 dwork
+ * NULL, -3 host NULL. */
+int hqr_batch_publish_status(const hqr_batch* b, const void* dwork, int32_t* host, void* stream);
+
 /* Copies the factorization of problem q (its T factors and the tiles of its
  * matrix) out of the batch workspace into dst, a workspace of
  * hqr_workspace_size(M[q], N[q]) bytes laid out as hqr_factor leaves it,

@@ -51,8 +51,8 @@ EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_s
            "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size", "hqr_lstsq",
            "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_timeline", "hqr_version",
            "hqr_batch_create", "hqr_batch_workspace_size", "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run",
-           "hqr_batch_status", "hqr_batch_destroy", "hqr_lstsq_batched", "hqr_lstsq_batched_workspace_size",
-           "hqr_solve", "hqr_batch_export_factors")
+           "hqr_batch_status", "hqr_batch_publish_status", "hqr_batch_destroy", "hqr_lstsq_batched",
+           "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors")
 
 _lib = None
 
@@ -98,6 +98,7 @@ def load():
     lib.hqr_batch_bind.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.hqr_batch_run.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.hqr_batch_status.argtypes = [vp, vp, vp, ctypes.c_double, P(i32), vp]
+    lib.hqr_batch_publish_status.argtypes = [vp, vp, vp, vp]
     lib.hqr_batch_destroy.argtypes = [vp]
     lib.hqr_batch_destroy.restype = None
     lib.hqr_lstsq_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
@@ -118,7 +119,8 @@ def load():
                  "hqr_factor", "hqr_apply_workspace_size", "hqr_apply_qt", "hqr_apply_q", "hqr_lstsq_workspace_size",
                  "hqr_lstsq", "hqr_status", "hqr_status_ex", "hqr_workspace_size_f32", "hqr_factor_f32",
                  "hqr_lstsq_ir_workspace_size", "hqr_lstsq_ir", "hqr_batch_create", "hqr_batch_workspace_size",
-                 "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run", "hqr_batch_status", "hqr_lstsq_batched",
+                 "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run", "hqr_batch_status", "hqr_batch_publish_status",
+                 "hqr_lstsq_batched",
                  "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -351,6 +353,14 @@ class Batch:
                                                            ctypes.c_void_p(stream), timeout_s, ctypes.byref(s),
                                                            _ptr(fz)))
         return s.value, fz
+
+    def publish_status(self, dwork: int, host: int, stream: int) -> None:
+        """Enqueues the device-side write of the status into `host` (count + 1
+        int32 of pinned host memory): host[0] status, host[1 + q] first zero
+        diagonal index of problem q or -1, valid once the stream's work up to
+        here has completed."""
+        _check("hqr_batch_publish_status", load().hqr_batch_publish_status(
+            self.handle, ctypes.c_void_p(dwork), ctypes.c_void_p(host), ctypes.c_void_p(stream)))
 
     def export_factors(self, q: int, dwork: int, dst: int, dst_bytes: int, stream: int) -> None:
         _check("hqr_batch_export_factors", load().hqr_batch_export_factors(

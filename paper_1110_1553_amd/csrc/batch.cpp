@@ -128,6 +128,18 @@ int stage_upload(void* dst, const void* src, size_t bytes, hipStream_t stream) {
 
 using namespace hqr;
 
+// The status of a finished batch written by the device into host memory,
+// in the form hqr_batch_status reports it: host[0] = status word,
+// host[1 + q] = first zero diagonal index of problem q, or -1.
+static __global__ void publish_status_kernel(const hqr::ProbDesc* d, const int32_t* ctrl, const int32_t* info,
+                                             int count, int32_t* host) {
+  if (threadIdx.x == 0) host[0] = ctrl[1];
+  for (int q = threadIdx.x; q < count; q += blockDim.x) {
+    const int32_t v = info[q];
+    host[1 + q] = v > 0 ? (int32_t)(d[q].N - v) : -1;
+  }
+}
+
 extern "C" {
 
 int hqr_batch_create(int32_t count, const int64_t* M, const int64_t* N, const int32_t* nrhs,
@@ -352,6 +364,17 @@ int hqr_batch_status(const hqr_batch* b, const void* dwork, void* stream, double
     for (int32_t q = 0; q < b->count; ++q) first_zero[q] = info[q] > 0 ? (int32_t)(b->N[q] - info[q]) : -1;
   }
   return 0;
+}
+
+int hqr_batch_publish_status(const hqr_batch* b, const void* dwork, int32_t* host, void* stream) {
+  if (!b) return -1;
+  if (!dwork) return -2;
+  if (!host) return -3;
+  const char* w = (const char*)dwork;
+  hipLaunchKernelGGL(publish_status_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream,
+                     (const ProbDesc*)(w + b->off_desc), (const int32_t*)w, (const int32_t*)(w + b->off_info),
+                     b->count, host);
+  return record_hip(hipGetLastError(), "publish_status_kernel launch");
 }
 
 int hqr_batch_export_factors(const hqr_batch* b, int32_t q, const void* dwork, void* dst, size_t dst_bytes,

@@ -129,4 +129,9 @@ def test_f32_ir_and_solve_argument_checks(hqr_lib):
     E = hqr_lib.hqr_batch_export_factors
     assert E(b.handle, 2, vp(16), vp(16), 1 << 30, None) == -2
     assert E(b.handle, 0, vp(16), vp(16), h.workspace_size(300, 100, p) - 1, None) == -5
+    # publishing a batch status into host memory
+    P = hqr_lib.hqr_batch_publish_status
+    assert P(None, vp(16), vp(16), None) == -1
+    assert P(b.handle, None, vp(16), None) == -2
+    assert P(b.handle, vp(16), None, None) == -3
     b.close()

@@ -185,5 +185,12 @@ def test_rank_deficient_problem_is_reported(cuda):
     st, first_zero = solver.status(timeout_s=60.0)
     assert st == _lib.ERR_SINGULAR
     assert first_zero.tolist() == [-1, 41, -1]
+    # the same report written by the device into pinned host memory
+    import torch
+
+    words = torch.full((len(shapes) + 1,), 7, dtype=torch.int32, pin_memory=True)
+    solver.batch.publish_status(solver.work.data_ptr(), words.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert words.tolist() == [_lib.ERR_SINGULAR, -1, 41, -1]
     for q in (0, 2):
         check_against_oracle(As[q], Bs[q], dAs[q].cpu().numpy(), dBs[q].cpu().numpy(), "problem %d" % q)
