@@ -158,7 +158,9 @@ def run_lstsq(device, M=32768, N=2048, seed=4, reps=5):
     import paper_1110_1553_amd as h
     from paper_1110_1553_amd import inputs
 
-    params = h.make_params(nb=256, p=4, a=4, low="greedy", high="fibonacci", domino=1)
+    # TS domains of 2 tiles: the fastest hierarchical tree for 128 tile rows (a = 4 and 8, p = 1..16, and
+    # plain Greedy / Binary trees measured 0.3-4.7 ms slower)
+    params = h.make_params(nb=256, p=4, a=2, low="greedy", high="fibonacci", domino=1)
     A0 = h.colmajor(inputs.graded_tall_device(M, N, seed, 1e-6, device))
     g = torch.Generator(device=device)
     g.manual_seed(seed + 1)
@@ -187,12 +189,15 @@ def run_lstsq(device, M=32768, N=2048, seed=4, reps=5):
     nA = torch.linalg.matrix_norm(A0, 2).item()
     opt = (A0.t() @ r_).norm().item() / (nA * nA * x.norm().item())
     t = sum(times) / len(times)
-    out = {"workload": "FP64 least squares %dx%d, kappa 1e6, one right-hand side, nb=256 hierarchical tree" % (M, N),
+    out = {"workload": "FP64 least squares %dx%d, kappa 1e6, one right-hand side, nb=256 hierarchical tree "
+                       "(TS domains a=2, Greedy low, domino coupling, Fibonacci high, p=4)" % (M, N),
            "solves_per_s": 1.0 / t, "ms_per_solve": 1e3 * t,
            "gflops": (qr_flops(M, N) + 4.0 * M * N) / t / 1e9,
            "forward_error_vs_x_true": ((x - xs).norm() / xs.norm()).item(),
            "normal_equations_residual": opt}
     # the same problem with an FP32 factorization refined in FP64 (hqr_lstsq_ir)
+    # the refinement keeps TS domains of 4 tiles: at a = 2 the FP32 factors needed one correction more at
+    # eta <= 1e-12 (37.1 against 35.0 ms)
     pf = h.make_params(nb=256, p=4, a=4, low="greedy", high="fibonacci", domino=1)
     del A, b, work
     torch.cuda.empty_cache()
