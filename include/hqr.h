@@ -390,6 +390,16 @@ int hqr_batch_publish_status(const hqr_batch* b, const void* dwork, int32_t* hos
 int hqr_batch_export_factors(const hqr_batch* b, int32_t q, const void* dwork, void* dst, size_t dst_bytes,
                              void* stream);
 
+/* hqr_batch_export_factors for every problem q with dst[q] not NULL, in one
+ * launch on `stream` (plus the upload of count small descriptors into the
+ * batch workspace, which must be the one bound last): each dst[q] (device
+ * memory of dst_bytes[q] >= hqr_workspace_size(M_q, N_q) bytes, owned by the
+ * caller) receives problem q's factors in the hqr_factor workspace layout,
+ * with zero control words.  The batch's run must have been enqueued before.
+ * Errors: -1 b NULL, -2 dwork NULL or not the bound workspace, -3 dst NULL,
+ * -4 dst_bytes NULL, -5 some dst_bytes[q] too small (nothing enqueued). */
+int hqr_batch_export_all(const hqr_batch* b, void* dwork, void* const* dst, const size_t* dst_bytes, void* stream);
+
 /* Frees the host batch object (the caller's device buffers are untouched). */
 void hqr_batch_destroy(hqr_batch* b);
 

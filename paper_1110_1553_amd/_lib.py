@@ -52,7 +52,7 @@ EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_s
            "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_timeline", "hqr_version",
            "hqr_batch_create", "hqr_batch_workspace_size", "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run",
            "hqr_batch_status", "hqr_batch_publish_status", "hqr_batch_destroy", "hqr_lstsq_batched",
-           "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors")
+           "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors", "hqr_batch_export_all")
 
 _lib = None
 
@@ -99,6 +99,7 @@ def load():
     lib.hqr_batch_run.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.hqr_batch_status.argtypes = [vp, vp, vp, ctypes.c_double, P(i32), vp]
     lib.hqr_batch_publish_status.argtypes = [vp, vp, vp, vp]
+    lib.hqr_batch_export_all.argtypes = [vp, vp, vp, vp, vp]
     lib.hqr_batch_destroy.argtypes = [vp]
     lib.hqr_batch_destroy.restype = None
     lib.hqr_lstsq_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
@@ -121,7 +122,7 @@ def load():
                  "hqr_lstsq_ir_workspace_size", "hqr_lstsq_ir", "hqr_batch_create", "hqr_batch_workspace_size",
                  "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run", "hqr_batch_status", "hqr_batch_publish_status",
                  "hqr_lstsq_batched",
-                 "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors"):
+                 "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors", "hqr_batch_export_all"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -361,6 +362,16 @@ class Batch:
         here has completed."""
         _check("hqr_batch_publish_status", load().hqr_batch_publish_status(
             self.handle, ctypes.c_void_p(dwork), ctypes.c_void_p(host), ctypes.c_void_p(stream)))
+
+    def export_all(self, dwork: int, dsts, dst_bytes, stream: int) -> None:
+        """export_factors for every problem q with dsts[q] (a device pointer)
+        not 0, in one launch."""
+        d = np.array([int(x or 0) for x in dsts], dtype=np.uint64)
+        n = np.array([int(x) for x in dst_bytes], dtype=np.uint64)
+        if d.size != self.count or n.size != self.count:
+            raise ValueError("one destination and size per problem")
+        _check("hqr_batch_export_all", load().hqr_batch_export_all(self.handle, ctypes.c_void_p(dwork), _ptr(d),
+                                                                   _ptr(n), ctypes.c_void_p(stream)))
 
     def export_factors(self, q: int, dwork: int, dst: int, dst_bytes: int, stream: int) -> None:
         _check("hqr_batch_export_factors", load().hqr_batch_export_factors(

@@ -33,6 +33,19 @@
 #include "layout.hpp"
 #include "task.hpp"
 
+namespace hqr {
+// One problem's factors copied out of a batch workspace into a workspace of
+// the single-problem layout (hqr_batch_export_all).  Byte offsets; every
+// region is 256-byte aligned and a multiple of 16 bytes long.
+struct ExportDesc {
+  char* dst;          // destination workspace, null: the problem is skipped
+  int64_t zero_bytes; // control words and counters at its start, cleared
+  int64_t tg_dst, tk_dst, tiles_dst;
+  int64_t tg_src, tk_src, tiles_src;  // in the batch workspace
+  int64_t tsz, asz;   // bytes of each T array, of the matrix tiles
+};
+}  // namespace hqr
+
 struct hqr_batch {
   int32_t count = 0;
   hqr_params p{};
@@ -42,7 +55,7 @@ struct hqr_batch {
   std::vector<hqr::ProbDesc> desc;  // offsets set at creation, caller pointers at bind
   std::vector<hqr::DevTask> tasks;  // merged dispatch order
   std::vector<int32_t> prob;        // problem of each task
-  size_t off_info = 0, off_cnt = 0, off_desc = 0, off_tasks = 0, off_prob = 0, off_data = 0, total = 0;
+  size_t off_info = 0, off_cnt = 0, off_desc = 0, off_tasks = 0, off_prob = 0, off_export = 0, off_data = 0, total = 0;
   int32_t max_nrhs = 0;             // widest back substitution (workgroups per problem)
   int64_t max_elems = 0;            // padded elements of the largest problem (copy grid)
   void* bound_work = nullptr;       // workspace the descriptors were uploaded to
@@ -140,6 +153,33 @@ static __global__ void publish_status_kernel(const hqr::ProbDesc* d, const int32
   }
 }
 
+// Every kept problem of a batch in one launch: workgroup row blockIdx.y
+// copies problem blockIdx.y, 16 bytes per thread and step.
+static __global__ void export_batched_kernel(const hqr::ExportDesc* e, const char* w) {
+  const hqr::ExportDesc d = e[blockIdx.y];
+  if (!d.dst) return;
+  const int64_t z = d.zero_bytes / 16, t = d.tsz / 16, a = d.asz / 16;
+  const int64_t total = z + 2 * t + a;
+  typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    u4v v = {0u, 0u, 0u, 0u};
+    char* o;
+    if (x < z) {
+      o = d.dst + 16 * x;
+    } else if (x < z + t) {
+      v = ((const u4v*)(w + d.tg_src))[x - z];
+      o = d.dst + d.tg_dst + 16 * (x - z);
+    } else if (x < z + 2 * t) {
+      v = ((const u4v*)(w + d.tk_src))[x - z - t];
+      o = d.dst + d.tk_dst + 16 * (x - z - t);
+    } else {
+      v = ((const u4v*)(w + d.tiles_src))[x - z - 2 * t];
+      o = d.dst + d.tiles_dst + 16 * (x - z - 2 * t);
+    }
+    *(u4v*)o = v;
+  }
+}
+
 extern "C" {
 
 int hqr_batch_create(int32_t count, const int64_t* M, const int64_t* N, const int32_t* nrhs,
@@ -219,6 +259,8 @@ int hqr_batch_create(int32_t count, const int64_t* M, const int64_t* N, const in
   off = align256(off + ntasks * sizeof(DevTask));
   b->off_prob = off;
   off = align256(off + ntasks * sizeof(int32_t));
+  b->off_export = off;
+  off = align256(off + (size_t)count * sizeof(ExportDesc));
   b->off_data = off;
   for (int32_t q = 0; q < count; ++q) {
     const Layout& L = lay[q];
@@ -399,6 +441,43 @@ int hqr_batch_export_factors(const hqr_batch* b, int32_t q, const void* dwork, v
     return rc;
   return record_hip(hipMemcpyAsync(o + L.tiles, w + d.tiles, asz, hipMemcpyDeviceToDevice, s),
                     "hipMemcpyAsync(tiles)");
+}
+
+int hqr_batch_export_all(const hqr_batch* b, void* dwork, void* const* dst, const size_t* dst_bytes, void* stream) {
+  if (!b) return -1;
+  if (!dwork || dwork != b->bound_work) return -2;
+  if (!dst) return -3;
+  if (!dst_bytes) return -4;
+  std::vector<ExportDesc> e((size_t)b->count);
+  int64_t units = 0;
+  for (int32_t q = 0; q < b->count; ++q) {
+    ExportDesc& x = e[q];
+    std::memset(&x, 0, sizeof(x));
+    if (!dst[q]) continue;
+    const Layout L = layout_for(b->M[q], b->N[q], b->p);
+    if (dst_bytes[q] < L.total) return -5;
+    const ProbDesc& d = b->desc[q];
+    x.dst = (char*)dst[q];
+    x.zero_bytes = (int64_t)L.tg;
+    x.tg_dst = (int64_t)L.tg;
+    x.tk_dst = (int64_t)L.tk;
+    x.tiles_dst = (int64_t)L.tiles;
+    x.tg_src = d.tg;
+    x.tk_src = d.tk;
+    x.tiles_src = d.tiles;
+    x.tsz = (int64_t)L.mt * L.nt * b->p.nb * 16 * (int64_t)sizeof(double);
+    x.asz = (int64_t)L.mt * L.nt * b->p.nb * b->p.nb * (int64_t)sizeof(double);
+    units = std::max<int64_t>(units, (x.zero_bytes + 2 * x.tsz + x.asz) / 16);
+  }
+  if (units == 0) return 0;
+  char* w = (char*)dwork;
+  if (int rc = stage_upload(w + b->off_export, e.data(), e.size() * sizeof(ExportDesc), (hipStream_t)stream))
+    return rc;
+  // workgroups per problem: about eight 16-byte steps per thread of the largest problem
+  const int64_t gx = std::min<int64_t>(1024, std::max<int64_t>(1, (units + 2047) / 2048));
+  hipLaunchKernelGGL(export_batched_kernel, dim3((unsigned)gx, (unsigned)b->count), dim3(256), 0,
+                     (hipStream_t)stream, (const ExportDesc*)(w + b->off_export), (const char*)w);
+  return record_hip(hipGetLastError(), "export_batched_kernel launch");
 }
 
 void hqr_batch_destroy(hqr_batch* b) { delete b; }

@@ -151,10 +151,9 @@ class GpuBackend:
             from . import Workspace
 
             with torch.cuda.stream(st):
-                for q, r in enumerate(reqs):
-                    w = Workspace(r.M, r.N, self.params, device=self.device)
-                    batch.export_factors(q, base, w.ptr, w.bytes, st.cuda_stream)
-                    kept.append((r, w))
+                for r in reqs:
+                    kept.append((r, Workspace(r.M, r.N, self.params, device=self.device)))
+            batch.export_all(base, [w.ptr for _, w in kept], [w.bytes for _, w in kept], st.cuda_stream)
         end = torch.cuda.Event(enable_timing=True)
         end.record(st)
         return {"batch": batch, "slot": slot, "base": base, "end": end, "kept": kept}

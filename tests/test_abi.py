@@ -134,4 +134,8 @@ def test_f32_ir_and_solve_argument_checks(hqr_lib):
     assert P(None, vp(16), vp(16), None) == -1
     assert P(b.handle, None, vp(16), None) == -2
     assert P(b.handle, vp(16), None, None) == -3
+    # exporting every problem's factors in one launch (b was never bound)
+    X = hqr_lib.hqr_batch_export_all
+    assert X(None, vp(16), vp(16), vp(16), None) == -1
+    assert X(b.handle, vp(16), vp(16), vp(16), None) == -2
     b.close()

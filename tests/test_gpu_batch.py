@@ -194,3 +194,35 @@ def test_rank_deficient_problem_is_reported(cuda):
     assert words.tolist() == [_lib.ERR_SINGULAR, -1, 41, -1]
     for q in (0, 2):
         check_against_oracle(As[q], Bs[q], dAs[q].cpu().numpy(), dBs[q].cpu().numpy(), "problem %d" % q)
+
+
+def test_export_all_matches_per_problem_export(cuda):
+    """hqr_batch_export_all writes the same bytes as hqr_batch_export_factors
+    problem by problem, and skips problems without a destination."""
+    import torch
+
+    import paper_1110_1553_amd as h
+
+    shapes = [(900, 37, 1), (1300, 300, 1), (500, 120, 2), (700, 256, 0)]
+    say("export of a batch's factors %s" % shapes)
+    params = h.make_params(nb=256, p=1, a=2, low="greedy", high="greedy")
+    As = [dev(inputs.gaussian(m, n, 900 + q)) for q, (m, n, r) in enumerate(shapes)]
+    Bs = [dev(inputs.gaussian(m, max(r, 1), 950 + q)[:, :r]) for q, (m, n, r) in enumerate(shapes)]
+    solver = h.BatchedLstsq(As, Bs, params, h.make_exec(spin_limit=SPIN))
+    solver.run()
+    s = torch.cuda.current_stream().cuda_stream
+    one = [torch.zeros(h.workspace_size(m, n, params), dtype=torch.uint8, device="cuda") for m, n, r in shapes]
+    for q, w in enumerate(one):
+        solver.batch.export_factors(q, solver.work.data_ptr(), w.data_ptr(), w.numel(), s)
+    allw = [torch.full((h.workspace_size(m, n, params),), 3, dtype=torch.uint8, device="cuda") for m, n, r in shapes]
+    for w in allw[:3]:
+        w.zero_()
+    dsts = [w.data_ptr() for w in allw[:3]] + [0]
+    solver.batch.export_all(solver.work.data_ptr(), dsts, [w.numel() for w in allw], s)
+    torch.cuda.synchronize()
+    for q in range(3):
+        assert torch.equal(one[q], allw[q]), "problem %d" % q
+    assert (allw[3] == 3).all()  # no destination: untouched
+    st, _ = solver.status(timeout_s=60.0)
+    assert st == 0
+
