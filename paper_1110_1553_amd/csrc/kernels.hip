@@ -455,11 +455,13 @@ __device__ __forceinline__ void stage_panel(const PanelPrefetch<E, NB>& pf, E* V
 //   C2: tile updated below the identity part (UNM: the tile itself).
 //   C1: killer tile (TS/TT).
 // TRANS applies Q^T (the panels in factorization order, T^T); otherwise Q
-// (the panels in reverse order, T).
+// (the panels in reverse order, T).  Only the first np panels are applied:
+// the panels after them are identities (T = 0, the zero padding beyond the
+// last matrix column of a ragged tile column).
 template <typename E, int NB, int KIND, bool TRANS, int CW>
 __device__ __forceinline__ void run_update(Smem<E, NB>& sm, const E* V, const E* T, E* C1, E* C2,
-                                           int64_t ld) {
-  constexpr int NP = NB / IB;
+                                           int64_t ld, int np = NB / IB) {
+  const int NP = __builtin_amdgcn_readfirstlane(np);
   const Lane L;
   const bool on = 16 * L.wave < CW;  // waves holding a strip of the chunk (uniform per wave)
   V4<E> acc[NB / 16];
@@ -1184,10 +1186,13 @@ __device__ __noinline__ void update_task(const LaunchArgs& a, const DevTask& tas
   const E* Tb = t_block<E>(T, a, NB, task.row, task.k);
   E* C1 = KIND == K_UNM ? nullptr : tile_ptr<E>(a, NB, task.killer, task.j) + colchunk;
   E* C2 = tile_ptr<E>(a, NB, task.row, task.j) + colchunk;
+  // panels of the factored tile column that hold matrix columns: four per
+  // 64-column block up to its last active block (task.pad & 0xff)
+  const int np = 4 * ((task.pad & 0xff) + 1) < NB / IB ? 4 * ((task.pad & 0xff) + 1) : NB / IB;
   if (NB >= 128 && (task.pad >> 8) == 2)
-    run_update<E, NB, KIND, true, 128>(smem<E, NB>(), V, Tb, C1, C2, NB);
+    run_update<E, NB, KIND, true, 128>(smem<E, NB>(), V, Tb, C1, C2, NB, np);
   else
-    run_update<E, NB, KIND, true, 64>(smem<E, NB>(), V, Tb, C1, C2, NB);
+    run_update<E, NB, KIND, true, 64>(smem<E, NB>(), V, Tb, C1, C2, NB, np);
 }
 
 // Block of 64 columns of B (nb x 64, column-major) of tile row r.
