@@ -74,7 +74,11 @@ def test_dag_counts_and_weight_match(hqr_lib):
         assert st["device_tasks"] == len(tasks) + updates  # 2 column chunks of 128 at nb = 256
 
 
-def test_survey_task_counts(hqr_lib):
+def test_task_counts_closed_form(hqr_lib):
+    # flat TS on 8 x 4 tiles: sum over k of 1 GEQRT, 7 - k TSQRT, 3 - k UNMQR
+    # and (7 - k)(3 - k) TSMQR = 32 + 21 + 12 + 5 tasks; 64 x 64 tiles: every
+    # tile below the diagonal is killed once (2016 kills, plus 64 GEQRT under
+    # flat TS, 2080 GEQRT under TT), each with its updates to the right
     import paper_1110_1553_amd as h
 
     assert h.dag_stats(8, 4, h.make_params(nb=64, a=8, low="flat"))["tasks"] == 70
