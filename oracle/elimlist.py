@@ -13,7 +13,9 @@ written from the paper's definitions:
 * Section III-A/B: the flat tree (Tables 1 and 3), the binary tree
   (Table 4) and the Greedy reduction (Table 5); the Fibonacci scheme is only
   named by the paper -- the construction used here is the reading recorded
-  in the design notes (parity unpinned by the paper).
+  in the design notes, pinned by the property of the cited scheme (each
+  panel repeats the previous one a row lower) and by a closed form of its
+  groups, not by values the paper prints.
 * Section IV: the hierarchical composition HQR with TS domains of a tiles
   (level 0), a low-level tree (level 1), the coupling ("domino") tree
   (level 2) and the high-level tree (level 3), rows mapped cyclically on a
@@ -62,33 +64,42 @@ def tree_binary(L: Sequence[int]):
 
 
 def tree_fibonacci(L: Sequence[int]):
-    """Fibonacci scheme of order 1 (named in Sections III-C and V; its
-    construction is not given in the paper -- reading of the design notes).
+    """Fibonacci scheme of order 1 (named in Sections III-C and V, where it
+    is credited to Modi and Clarke; its construction is not given in the
+    paper -- reading of the design notes).
 
-    Positions 1..s-1 are cut, from the top, into consecutive groups of sizes
-    1, 2, 3, ... (the last one truncated).  With G groups, group g is killed in
-    round G - g + 1 (bottom group first); a victim at position v in a group of
-    actual size z is killed by position v - z, i.e. the z rows right above the
-    group kill it in natural order."""
+    Positions 1..s-1 are cut, from the top, into consecutive groups of
+    nominal sizes 1, 2, 3, ... (the last group may be cut short by the end of
+    the list).  With G groups, group g is killed in round G - g + 1 (bottom
+    group first), and the victim at position v of group g is killed by
+    position v - g, the row g places above it.  The killer of a position
+    depends on the position only, not on the length of the list, so the next
+    panel's list (one row shorter, starting one row lower) gets the same
+    pattern shifted down by one row: the property of the cited scheme that
+    each column repeats the previous one a row lower.  The victims of a round
+    and their killers are distinct rows that are still alive (the killers of
+    group g lie in groups g - 1 and g - 2)."""
     s = len(L)
     groups = []
     pos, size = 1, 1
     while pos < s:
         z = min(size, s - pos)
-        groups.append((pos, z))
+        groups.append((pos, z, size))
         pos += z
         size += 1
     G = len(groups)
     out = []
-    for g, (start, z) in enumerate(groups, 1):
+    for g, (start, z, nominal) in enumerate(groups, 1):
         for v in range(start, start + z):
-            out.append((L[v], L[v - z], G - g + 1))
+            out.append((L[v], L[v - nominal], G - g + 1))
     return out
 
 
 def tree_chain(L: Sequence[int]):
     """Domino chain (Section IV-B, level 2): bottom first, each row is killed
-    by the row right above it."""
+    by the row right above it.  The paper shows the domino level on one
+    example only, whose coupling lists hold two rows; for longer lists this
+    chain is a reading (design notes, D1), pinned by that example alone."""
     s = len(L)
     return [(L[j], L[j - 1], s - j) for j in range(s - 1, 0, -1)]
 

@@ -27,20 +27,17 @@ static void tree_binary(const std::vector<int32_t>& L, std::vector<Kill>& out) {
 }
 
 static void tree_fibonacci(const std::vector<int32_t>& L, std::vector<Kill>& out) {
-  // Order-1 Fibonacci scheme: positions 1..s-1 form groups of 1, 2, 3, ...
-  // rows (last one truncated); the bottom group dies first, each group killed
-  // by the rows directly above it in natural order.
+  // Order-1 Fibonacci scheme: positions 1..s-1 form groups of nominal sizes
+  // 1, 2, 3, ... (the last one cut short by the end of the list); the bottom
+  // group dies first, and the victim at position v of group g is killed by
+  // position v - g.  The killer depends on the position only, so each panel
+  // repeats the previous panel's pattern one row lower.
   const int32_t s = (int32_t)L.size();
-  std::vector<std::pair<int32_t, int32_t>> groups;  // (first position, size)
-  for (int32_t pos = 1, size = 1; pos < s; pos += size, ++size) {
-    int32_t z = std::min(size, s - pos);
-    groups.push_back({pos, z});
-    if (z < size) break;
-  }
-  const int32_t G = (int32_t)groups.size();
-  for (int32_t g = 0; g < G; ++g) {
-    const int32_t first = groups[g].first, z = groups[g].second;
-    for (int32_t v = first; v < first + z; ++v) out.push_back({L[v], L[v - z], G - g});
+  int32_t G = 0;
+  for (int32_t pos = 1, size = 1; pos < s; pos += size, ++size) ++G;
+  for (int32_t pos = 1, g = 1; pos < s; pos += g, ++g) {
+    const int32_t end = std::min(pos + g, s);
+    for (int32_t v = pos; v < end; ++v) out.push_back({L[v], L[v - g], G - g + 1});
   }
 }
 
@@ -103,6 +100,7 @@ int check_params(const hqr_params& p) {
   if (p.high < HQR_FLAT || p.high > HQR_FIBONACCI) return -6;
   if (p.coupling < HQR_FLAT || p.coupling > HQR_CHAIN) return -7;
   if (p.domino != 0 && p.domino != 1) return -8;
+  if (p.precision < HQR_PREC_FP64 || p.precision > HQR_PREC_BF16) return -9;
   return 0;
 }
 

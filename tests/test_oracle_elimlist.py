@@ -12,6 +12,7 @@
 """
 import itertools
 import os
+import math
 import random
 
 import pytest
@@ -130,13 +131,48 @@ def test_named_special_cases():
 
 
 def test_fibonacci_construction_example():
-    # groups of sizes 1,2,3,4,4 (truncated) for 15 rows; the bottom group goes first and is
-    # killed by the rows right above it
+    # 15 rows: groups of nominal sizes 1, 2, 3, 4, 5 from the top, the last one cut to 4 rows by the
+    # end of the list; the bottom group goes first, each victim killed by the row g places above it
     trip = el.tree_fibonacci(list(range(15)))
     got = {v: (kk, r) for v, kk, r in trip}
+    assert sorted(got) == list(range(1, 15))
     assert got[1] == (0, 5) and got[2] == (0, 4) and got[3] == (1, 4)
     assert [got[v] for v in (4, 5, 6)] == [(1, 3), (2, 3), (3, 3)]
-    assert [got[v] for v in (11, 12, 13, 14)] == [(7, 1), (8, 1), (9, 1), (10, 1)]
+    assert [got[v] for v in (7, 8, 9, 10)] == [(3, 2), (4, 2), (5, 2), (6, 2)]
+    assert [got[v] for v in (11, 12, 13, 14)] == [(6, 1), (7, 1), (8, 1), (9, 1)]
+
+
+def _fib_group(v):
+    """Group of position v >= 1 in closed form: the least g with g (g + 1) / 2 >= v."""
+    g = (math.isqrt(8 * v) - 1) // 2
+    while g * (g + 1) // 2 < v:
+        g += 1
+    return g
+
+
+def test_fibonacci_closed_form():
+    # killer position v - g(v), round G - g(v) + 1 with G = g(s - 1), for every list length
+    for s in range(1, 200):
+        trip = el.tree_fibonacci(list(range(s)))
+        assert len(trip) == s - 1
+        G = _fib_group(s - 1) if s > 1 else 0
+        for v, kk, r in trip:
+            g = _fib_group(v)
+            assert (kk, r) == (v - g, G - g + 1), (s, v)
+
+
+def test_fibonacci_panels_shift_one_row():
+    # the cited scheme repeats each column's pattern one row lower in the next column: in a
+    # single-tree run, the killer of row i in panel k is one more than the killer of row i - 1 in
+    # panel k - 1 (a wrong group offset anywhere breaks this for some list length)
+    for mt in range(2, 48):
+        for nt in (1, 2, min(mt, 5), mt):
+            recs = el.hqr_elimlist(mt, nt, p=1, a=1, low=el.FIBONACCI)
+            el.validate(mt, nt, recs)
+            killer = {(k, i): piv for (k, i, piv, _, _, _) in recs}
+            for (k, i), piv in killer.items():
+                if k > 0:
+                    assert piv == killer[(k - 1, i - 1)] + 1, (mt, nt, k, i)
 
 
 TREES = [el.FLAT, el.BINARY, el.GREEDY, el.FIBONACCI]
