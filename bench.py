@@ -92,6 +92,23 @@ def make_input(w, device):
     return inputs.graded_device(w["M"], w["seed"], 1e-8, device)
 
 
+def mean_std(xs):
+    m = sum(xs) / len(xs)
+    v = sum((x - m) ** 2 for x in xs) / (len(xs) - 1) if len(xs) > 1 else 0.0
+    return m, v ** 0.5
+
+
+def host_plan_ms(M, N, params):
+    """Host time of the elimination list, task graph and dispatch order (hqr_plan_tasks builds them
+    from scratch; hqr_factor caches the result per shape and tree)."""
+    from paper_1110_1553_amd import _lib
+
+    nb = params.nb
+    t = time.perf_counter()
+    _lib.plan_tasks((M + nb - 1) // nb, (N + nb - 1) // nb, params)
+    return 1e3 * (time.perf_counter() - t)
+
+
 def run_workload(name, steps, warmup, device, keep_result=False):
     import torch
 
@@ -100,6 +117,7 @@ def run_workload(name, steps, warmup, device, keep_result=False):
     w = WORKLOADS[name]
     M, N = w["M"], w["N"]
     params = h.make_params(**w["params"])
+    plan_ms = host_plan_ms(M, N, params)
     pristine = h.colmajor(make_input(w, device))
     f32 = w.get("dtype") == "f32"
     if f32:
@@ -115,11 +133,17 @@ def run_workload(name, steps, warmup, device, keep_result=False):
     copies = [pristine.clone() for _ in range(steps)]
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    # events around the persistent launch alone (recorded by the library on the same stream)
+    kb = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ke = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for e in kb + ke:
+        e.record(stream)  # creates the underlying hipEvent
     torch.cuda.synchronize(device)
     t0 = time.perf_counter()
     for s in range(steps):
         starts[s].record(stream)
-        h.factor(copies[s], params, work=work, stream=stream, check=False)
+        ex = h.make_exec(ev_begin=kb[s].cuda_event, ev_end=ke[s].cuda_event)
+        h.factor(copies[s], params, exec_=ex, work=work, stream=stream, check=False)
         ends[s].record(stream)
     torch.cuda.synchronize(device)
     wall = time.perf_counter() - t0
@@ -127,21 +151,32 @@ def run_workload(name, steps, warmup, device, keep_result=False):
     if status != 0:
         raise RuntimeError("device status %d in workload %s" % (status, name))
     ev = [starts[s].elapsed_time(ends[s]) / 1e3 for s in range(steps)]
+    kev = [kb[s].elapsed_time(ke[s]) / 1e3 for s in range(steps)]
     fl = qr_flops(M, N)
+    launch_s, launch_std = mean_std(ev)
+    kernel_s, kernel_std = mean_std(kev)
+    peak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
     out = {
         "workload": name,
         "label": w["label"],
         "M": M, "N": N,
         "params": w["params"],
+        "steps": steps, "warmup": warmup,
         "wall_s": wall,
         "ms_per_step": 1e3 * wall / steps,
         "gflops": fl * steps / wall / 1e9,
-        "launch_s": sum(ev) / len(ev),
+        "launch_s": launch_s,
+        "launch_ms_std": 1e3 * launch_std,
         "launch_s_min": min(ev),
         "launch_s_max": max(ev),
-        "tflops_launch": fl / (sum(ev) / len(ev)) / 1e12,
+        "tflops_launch": fl / launch_s / 1e12,
+        "kernel_s": kernel_s,
+        "kernel_ms_std": 1e3 * kernel_std,
+        "tflops_kernel": fl / kernel_s / 1e12,
+        "host_plan_ms": plan_ms,
     }
-    out["frac_peak"] = out["tflops_launch"] / (PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS)
+    out["frac_peak"] = out["tflops_launch"] / peak
+    out["frac_peak_kernel"] = out["tflops_kernel"] / peak
     result = copies[0] if keep_result else None
     host_sample = None
     if keep_result:
@@ -293,8 +328,21 @@ def run_serving(device, count=4096, budget_gib=8, seed=5, load=0.8, tune_sample=
     return out
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sample):
-    """The oracle (unblocked Householder QR) on a bounded sample of the workload."""
+    """The oracle (unblocked Householder QR) on the whole benchmark matrix with the host's threads (up
+    to 16), and on its leading 16384 x 512 block with one thread.  Returns the record and the
+    oracle's factored array (its upper triangle is R)."""
     import numpy as np
 
     from oracle import qr as oq
@@ -303,10 +351,34 @@ def cpu_baseline(sample):
     A = np.asfortranarray(sample)
     m, n = A.shape
     t = time.perf_counter()
-    oq.factor(A, nthreads=threads)
+    F, _ = oq.factor(A, nthreads=threads)
     dt = time.perf_counter() - t
-    return {"value": qr_flops(m, n) / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": "oracle QR of the whole %dx%d benchmark matrix, copied to the host (%.1f s)" % (m, n, dt)}, A
+    ms, ns = min(m, 16384), min(n, 512)
+    t = time.perf_counter()
+    oq.factor(np.asfortranarray(A[:ms, :ns]), nthreads=1)
+    dt1 = time.perf_counter() - t
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    rec = {"value": qr_flops(m, n) / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": "oracle QR of the whole %dx%d benchmark matrix, copied to the host (%.1f s on %d threads)"
+                     % (m, n, dt, threads),
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(), "cpus_available": avail,
+           "single_thread": {"value": qr_flops(ms, ns) / dt1 / 1e9, "unit": "GFLOP/s",
+                             "sample": "oracle QR of the leading %dx%d block, 1 thread (%.1f s)" % (ms, ns, dt1)}}
+    return rec, F
+
+
+def r_parity(R_gpu, F_ref):
+    """Relative Frobenius error of the sign-normalised R against the oracle's."""
+    import numpy as np
+
+    n = R_gpu.shape[1]
+    Rg, Rr = np.triu(R_gpu[:n, :n]), np.triu(F_ref[:n, :n])
+    dg = np.where(np.diagonal(Rg) < 0, -1.0, 1.0)
+    dr = np.where(np.diagonal(Rr) < 0, -1.0, 1.0)
+    return float(np.linalg.norm(Rg * dg[:, None] - Rr * dr[:, None]) / np.linalg.norm(Rr))
 
 
 def main():
@@ -315,8 +387,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tall-hqr", choices=sorted(WORKLOADS))
-    ap.add_argument("--secondary", default="tall-flat,tall-binary,square-greedy,square-flat,tall-hqr-f32",
-                    help="comma-separated workloads also timed (1 step each after 1 warm-up); empty for none")
+    ap.add_argument("--secondary", default="square-flat,square-greedy,tall-flat,tall-binary,tall-hqr-f32",
+                    help="comma-separated workloads also timed (--sec-steps steps each after 2 warm-ups); empty "
+                         "for none")
+    ap.add_argument("--sec-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", type=int, default=4096, help="requests in the serving trace (0: skip serving)")
     ap.add_argument("--no-lstsq", action="store_true", help="skip the least-squares measurement")
@@ -328,16 +402,22 @@ def main():
 
     device = torch.device("cuda:0")
     torch.cuda.set_device(device)
-    primary, _, host_sample = run_workload(args.workload, args.steps, args.warmup, device, keep_result=True)
-    print("bench: %s %.3f ms/step" % (args.workload, primary["ms_per_step"]), file=sys.stderr, flush=True)
+    primary, result, host_sample = run_workload(args.workload, args.steps, args.warmup, device, keep_result=True)
+    R_gpu = result[:primary["N"], :primary["N"]].cpu().numpy() if result is not None else None
+    del result
+    print("bench: %s %.3f ms/step (kernel %.3f ms)" % (args.workload, primary["ms_per_step"],
+                                                      1e3 * primary["kernel_s"]), file=sys.stderr, flush=True)
     secondary = []
     for name in [s for s in args.secondary.split(",") if s]:
         if name == args.workload:
             continue
-        res, _, _ = run_workload(name, 1, 1, device)
-        print("bench: %s %.3f ms/step" % (name, res["ms_per_step"]), file=sys.stderr, flush=True)
-        secondary.append({k: res[k] for k in ("workload", "label", "ms_per_step", "gflops", "tflops_launch",
-                                              "frac_peak")})
+        res, _, _ = run_workload(name, args.sec_steps, 2, device)
+        print("bench: %s %.3f ms/step (kernel %.3f +- %.3f ms)" % (name, res["ms_per_step"], 1e3 * res["kernel_s"],
+                                                                  res["kernel_ms_std"]), file=sys.stderr, flush=True)
+        secondary.append({k: res[k] for k in ("workload", "label", "steps", "warmup", "ms_per_step", "gflops",
+                                              "tflops_launch", "frac_peak", "launch_ms_std", "kernel_s",
+                                              "kernel_ms_std", "tflops_kernel", "frac_peak_kernel",
+                                              "host_plan_ms")})
     lstsq = None
     if not args.no_lstsq:
         lstsq = run_lstsq(device)
@@ -348,9 +428,19 @@ def main():
         print("bench: serving %.0f solves/s p50 %.2f ms p99 %.2f ms" % (
             serving["solves_per_s"], serving["p50_ms"], serving["p99_ms"]), file=sys.stderr, flush=True)
     cpu = None
+    parity = None
     if not args.no_cpu_baseline and host_sample is not None:
-        cpu, _ = cpu_baseline(host_sample)
+        cpu, F_ref = cpu_baseline(host_sample)
         print("bench: cpu baseline %s" % cpu["sample"], file=sys.stderr, flush=True)
+        if R_gpu is not None and primary["params"].get("precision", "fp64") == "fp64" and \
+                WORKLOADS[args.workload].get("dtype") != "f32":
+            err = r_parity(R_gpu, F_ref)
+            parity = {"rel_err_R": err, "tol": 1e-12, "ok": bool(err <= 1e-12),
+                      "reference": "sign-normalised R of the oracle's QR of the same %dx%d matrix (the "
+                                   "cpu_baseline run), against the R of the first timed step"
+                                   % (primary["M"], primary["N"])}
+            print("bench: parity of R against the oracle %.3e" % err, file=sys.stderr, flush=True)
+        del F_ref
     w = WORKLOADS[args.workload]
     f32 = w.get("dtype") == "f32"
     peak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
@@ -369,18 +459,29 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["label"], "M": w["M"], "N": w["N"], "tree": w["params"],
                    "frac_peak": round(primary["frac_peak"], 4)},
-        "roofline": {"bound": "mfma", "achieved": round(primary["tflops_launch"], 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(primary["frac_peak"], 4),
+        "roofline": {"bound": "mfma", "achieved": round(primary["tflops_kernel"], 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(primary["frac_peak_kernel"], 4),
                      "traffic": traffic_for(args.workload), "traffic_unit": "bytes per launch (HBM read + write)",
                      "kernel": "persistent_kernel<%s, 256> (all tile kernels of one factorization)" % (
                          "float" if f32 else "double"),
-                     "launch_ms": round(1e3 * primary["launch_s"], 3)},
+                     "flops_per_launch": qr_flops(primary["M"], primary["N"]),
+                     "kernel_ms": round(1e3 * primary["kernel_s"], 3),
+                     "kernel_ms_std": round(primary["kernel_ms_std"], 3),
+                     "timing": "HIP events recorded by the library right before and after the persistent launch "
+                               "(hqr_exec.ev_begin/ev_end), mean over the timed steps",
+                     "whole_call_ms": round(1e3 * primary["launch_s"], 3),
+                     "whole_call_frac": round(primary["frac_peak"], 4)},
+        "host_plan_ms": round(primary["host_plan_ms"], 2),
+        "parity": parity,
         "cpu_baseline": cpu,
         "secondary": secondary,
         "lstsq": lstsq,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)
+    if parity is not None and not parity["ok"]:
+        print("bench.py: R differs from the oracle's by %.3e (> 1e-12)" % parity["rel_err_R"], file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -59,7 +59,18 @@ enum {
   HQR_ERR_INTERNAL = 5,   /* internal inconsistency (bug) */
   HQR_ERR_INVALID_LIST = 6, /* an elimination list breaks the rules of Section II */
   HQR_ERR_TIMEOUT = 7,      /* hqr_status_ex: the stream did not finish in time */
-  HQR_ERR_SINGULAR = 8      /* hqr_lstsq: R has a zero diagonal entry (reported by hqr_status) */
+  HQR_ERR_SINGULAR = 8,     /* hqr_lstsq: R has a zero diagonal entry (reported by hqr_status) */
+  HQR_ERR_FACTORS = 9       /* apply/solve: the workspace does not hold the factorization its arguments
+                               describe (other shape, tile size, tree or precision, or none); nothing was
+                               applied (reported by hqr_status on the apply workspace) */
+};
+
+/* Arithmetic of the tile kernels (hqr_params.precision). */
+enum {
+  HQR_PREC_FP64 = 0, /* FP64 tiles, FP64 MFMA (hqr_factor, hqr_lstsq, batches) */
+  HQR_PREC_FP32 = 1, /* FP32 tiles, FP32 MFMA (hqr_factor_f32, hqr_lstsq_ir) */
+  HQR_PREC_BF16 = 2  /* FP32 tiles; the block-reflector products take their operands rounded to BF16
+                        and accumulate in FP32 on the BF16 MFMA (hqr_factor_f32, hqr_lstsq_ir) */
 };
 
 /* Parameters of the hierarchical algorithm (Section IV-A and V-A).
@@ -73,7 +84,11 @@ enum {
  *   low       level-1 tree inside a cluster (FLAT, BINARY, GREEDY, FIBONACCI).
  *   high      level-3 tree over the p top tiles of a panel (same choices).
  *   coupling  level-2 tree (CHAIN is the domino scheme; any tree is allowed).
- *   domino    1 = coupling level on, 0 = off. */
+ *   domino    1 = coupling level on, 0 = off.
+ *   precision HQR_PREC_*: FP64 for the double entry points; for the float
+ *             ones (hqr_factor_f32, hqr_lstsq_ir) FP32 (0 is read as FP32
+ *             there) or BF16 operands with FP32 accumulation.  It does not
+ *             change the elimination list or the task graph. */
 typedef struct hqr_params {
   int32_t nb;
   int32_t ib;
@@ -83,7 +98,17 @@ typedef struct hqr_params {
   int32_t high;
   int32_t coupling;
   int32_t domino;
+  int32_t precision;
 } hqr_params;
+
+/* A finished factorization as seen from the host: the shape, parameters and
+ * precision given to hqr_factor / hqr_factor_f32 / hqr_lstsq, and the
+ * workspace that holds its T factors and factored tiles.  It points into that
+ * workspace (and the tiles copied back into dA) without owning them: keep the
+ * workspace unchanged while the handle is used.  Created by those entry
+ * points when their `out` argument is not NULL; freed by
+ * hqr_factors_destroy.  The handle is host memory only. */
+typedef struct hqr_factors hqr_factors;
 
 /* Execution controls of the persistent scheduler (not part of the algorithm).
  *   workers     persistent workgroups; 0 = one per free slot on the device
@@ -96,11 +121,19 @@ typedef struct hqr_params {
  *   spin_limit  polls of the dependency counters of one task before the
  *               launch is aborted (every workgroup stops taking tasks) and
  *               HQR_ERR_WATCHDOG is reported; 0 = a built-in limit of a few
- *               seconds of polling. */
+ *               seconds of polling.
+ *   ev_begin, ev_end  NULL, or hipEvent_t handles (created by the caller)
+ *               recorded on the call's stream right before and right after
+ *               the persistent launch of a factorization (hqr_factor,
+ *               hqr_factor_f32, hqr_lstsq, hqr_batch_run): the time between
+ *               them is the tile kernels' alone, without the copies into and
+ *               out of the workspace. */
 typedef struct hqr_exec {
   int32_t workers;
   int32_t order;
   int64_t spin_limit;
+  void* ev_begin;
+  void* ev_end;
 } hqr_exec;
 
 /* One elimination elim(victim, killer, k) (Section II).  `level` is the
@@ -190,14 +223,21 @@ int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* b
  *           tile-contiguous copy, filled from dA before the launch and copied
  *           back after it, on `stream`.
  *   exec    NULL for defaults.
+ *   out     NULL, or receives a new hqr_factors handle of this
+ *           factorization (for hqr_factors_apply_qt / _apply_q / _solve);
+ *           free it with hqr_factors_destroy.  Set only on success.
  * Errors: -1 if dA is NULL, -2 if M < N or M < 1 (or more than 65535 tile
- * rows), -3 if N < 1, -4 if lda < M, -5 bad params, -6 bad exec.order,
- * -7 if dwork is NULL, -8 workspace too small.  Runtime failures inside the launch (watchdog) are
- * reported by hqr_status.  The first call for a given (tile grid, params,
- * exec.order) builds the task plan on the host and uploads it to device
- * memory owned by the library (kept until hqr_release_plans). */
+ * rows), -3 if N < 1, -4 if lda < M, -5 bad params (or precision not FP64),
+ * -6 bad exec.order, -7 if dwork is NULL, -8 workspace too small;
+ * HQR_ERR_NOMEM if the handle cannot be allocated.  Runtime failures inside
+ * the launch (watchdog) are reported by hqr_status.
+ * Ownership: the caller owns dA and dwork.  The first call for a given (tile
+ * grid, params, exec.order) builds the task plan on the host and uploads it
+ * to device memory that the library allocates itself (hipMalloc, about 24
+ * bytes per task) and keeps until hqr_release_plans; this is the only device
+ * memory the library allocates on this path. */
 int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params,
-               const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
+               const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream, hqr_factors** out);
 
 /* ---- Single precision ----
  *
@@ -209,9 +249,11 @@ int hqr_workspace_size_f32(int64_t M, int64_t N, const hqr_params* params, size_
 
 /* QR of the column-major float matrix dA (M x N, lda >= M) in place, as
  * hqr_factor: R in the upper triangle, the Householder vectors below it,
- * the T factors (float) in dwork.  Errors as hqr_factor. */
+ * the T factors (float) in dwork.  params->precision selects FP32 (0 or 1)
+ * or BF16 operands with FP32 accumulation (2) for the block-reflector
+ * products.  out as for hqr_factor.  Errors as hqr_factor. */
 int hqr_factor_f32(float* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params, const hqr_exec* exec,
-                   void* dwork, size_t work_bytes, void* stream);
+                   void* dwork, size_t work_bytes, void* stream, hqr_factors** out);
 
 /* Bytes of the second workspace that hqr_apply_qt and hqr_apply_q need for a
  * right-hand side B of M rows and nrhs columns: a
@@ -228,9 +270,15 @@ int hqr_apply_workspace_size(int64_t M, int32_t nrhs, const hqr_params* params, 
  *   bwork         device workspace of hqr_apply_workspace_size(M, nrhs)
  *                 bytes (scratch; its status word is read by hqr_status).
  * Asynchronous on `stream`, which must be the factorization's stream or
- * ordered after it.  Errors: -2 M < N or M < 1, -3 N < 1, -4 bad params,
- * -6 dwork NULL, -7 work_bytes too small for (M, N), -8 dB NULL,
- * -9 ldb < M, -10 nrhs < 1, -11 bwork NULL, -12 bwork too small. */
+ * ordered after it.  dwork may be the workspace of hqr_factor or of
+ * hqr_lstsq (any nrhs) with the same (M, N, params): the T factors and
+ * tiles sit at the same offsets in both.  The launch first compares the
+ * signature that the factorization wrote into dwork's control words with
+ * (M, N, params); on a mismatch nothing is applied, B is left as it was, and
+ * hqr_status(bwork) reports HQR_ERR_FACTORS.  Errors: -2 M < N or M < 1, -3
+ * N < 1, -4 bad params, -6 dwork NULL, -7 work_bytes too small for (M, N),
+ * -8 dB NULL, -9 ldb < M, -10 nrhs < 1, -11 bwork NULL, -12 bwork too
+ * small. */
 int hqr_apply_qt(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* exec, const void* dwork,
                  size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
                  void* stream);
@@ -259,9 +307,35 @@ int hqr_lstsq_workspace_size(int64_t M, int64_t N, int32_t nrhs, const hqr_param
  * reported by hqr_status(dwork) as HQR_ERR_SINGULAR with detail[0] = its
  * index (the solution is then not finite).  Errors: -1 dA NULL, -2 M < N or
  * M < 1, -3 N < 1, -4 lda < M, -5 dB NULL, -6 ldb < M, -7 nrhs < 1, -8 bad
- * params, -9 bad exec.order, -10 dwork NULL, -11 dwork too small. */
+ * params, -9 bad exec.order, -10 dwork NULL, -11 dwork too small.  out
+ * (may be NULL) receives a handle of the factorization, as for
+ * hqr_factor. */
 int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t ldb, int32_t nrhs,
-              const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream);
+              const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream,
+              hqr_factors** out);
+
+/* ---- Factorization handles ----
+ *
+ * The same operations as hqr_apply_qt / hqr_apply_q / hqr_solve, with the
+ * shape, parameters, precision and workspace taken from a handle instead of
+ * repeated by the caller.  bwork: hqr_factors_apply_workspace_size bytes.
+ * Errors: -1 f NULL, -3 dB NULL, -4 ldb < M, -5 nrhs < 1, -6 bwork NULL,
+ * -7 bwork too small; hqr_factors_solve returns -1 for FP32/BF16 factors
+ * (it solves with a double R).  A workspace overwritten by another
+ * factorization since the handle was made is reported as for hqr_apply_qt. */
+int hqr_factors_apply_workspace_size(const hqr_factors* f, int32_t nrhs, size_t* bytes);
+int hqr_factors_apply_qt(const hqr_factors* f, const hqr_exec* exec, double* dB, int64_t ldb, int32_t nrhs,
+                         void* bwork, size_t bwork_bytes, void* stream);
+int hqr_factors_apply_q(const hqr_factors* f, const hqr_exec* exec, double* dB, int64_t ldb, int32_t nrhs,
+                        void* bwork, size_t bwork_bytes, void* stream);
+int hqr_factors_solve(const hqr_factors* f, const hqr_exec* exec, double* dB, int64_t ldb, int32_t nrhs,
+                      void* bwork, size_t bwork_bytes, void* stream);
+/* Shape, parameters (precision included) and workspace of a handle; any
+ * output may be NULL.  Errors: -1 f NULL. */
+int hqr_factors_query(const hqr_factors* f, int64_t* M, int64_t* N, hqr_params* params, const void** dwork,
+                      size_t* work_bytes);
+/* Frees the handle (NULL is ignored); the workspace and dA are untouched. */
+void hqr_factors_destroy(hqr_factors* f);
 
 /* ---- Mixed-precision least squares ----
  *
@@ -291,8 +365,9 @@ int hqr_lstsq_ir_workspace_size(int64_t M, int64_t N, const hqr_params* params, 
  * (b - A x at convergence).  The iterate is judged by the normwise backward
  * error of the augmented system, eta = sqrt(||f||^2 + ||g||^2) /
  * (||A||_F (||x|| + ||r||) + ||b||); the loop stops when eta <= tol, when
- * a correction did not lower eta, or after max_iter corrections; info (may
- * be NULL) reports the count and the eta history.  The forward error of x
+ * a correction did not lower eta (the iterate before that correction is
+ * returned, with its eta), or after max_iter corrections; info (may be
+ * NULL) reports the count of corrections kept and the eta history.  The forward error of x
  * is about kappa(A) times the final eta: tol near the FP64 unit roundoff
  * (1e-15) gives FP64 accuracy.  Synchronizes `stream` once per correction (eta is read on the
  * host).  Errors: -1 dA NULL, -2 M < N or

@@ -17,14 +17,15 @@ this package only marshals arguments to it:
 PyTorch supplies device memory and streams only.
 """
 from . import _lib
-from ._lib import (BINARY, CHAIN, FIBONACCI, FLAT, GREEDY, OPS, Exec, HQRError, Params, apply_workspace_size,
-                   dag_stats, elimlist, lstsq_workspace_size, make_exec, make_params, release_plans, validate, version,
-                   workspace_size)
+from ._lib import (BINARY, CHAIN, FIBONACCI, FLAT, GREEDY, OPS, Exec, Factors, HQRError, Params,
+                   apply_workspace_size, dag_stats, elimlist, lstsq_workspace_size, make_exec, make_params,
+                   release_plans, validate, version, workspace_size)
 
-__all__ = ["FLAT", "BINARY", "GREEDY", "FIBONACCI", "CHAIN", "OPS", "Params", "Exec", "HQRError", "make_params",
+__all__ = ["FLAT", "BINARY", "GREEDY", "FIBONACCI", "CHAIN", "OPS", "Params", "Exec", "Factors", "HQRError",
+           "make_params",
            "make_exec", "elimlist", "validate", "dag_stats", "workspace_size", "apply_workspace_size",
            "lstsq_workspace_size", "factor",
-           "apply_qt", "apply_q", "solve", "lstsq", "lstsq_ir", "lstsq_batched", "BatchedLstsq", "colmajor", "r_of", "Workspace", "ApplyWorkspace", "status",
+           "apply_qt", "apply_q", "solve", "lstsq", "factors_run", "lstsq_ir", "lstsq_batched", "BatchedLstsq", "colmajor", "r_of", "Workspace", "ApplyWorkspace", "status",
            "release_plans", "version"]
 
 
@@ -86,10 +87,11 @@ def _device_status(work, s, what, timeout_s=0.0):
     return st
 
 
-def factor(A, params, exec_=None, work=None, stream=None, check=True, timeout_s=0.0):
+def factor(A, params, exec_=None, work=None, stream=None, check=True, timeout_s=0.0, handle=False):
     """In-place QR of the column-major float64 (or float32: FP32 tile
     kernels) CUDA tensor ``A`` (M x N, strides (1, lda)).  Returns the
-    workspace (it holds the T factors)."""
+    workspace (it holds the T factors), or (workspace, :class:`Factors`)
+    with ``handle``."""
     import torch
 
     if A.dtype not in (torch.float64, torch.float32) or not A.is_cuda or A.dim() != 2:
@@ -103,14 +105,14 @@ def factor(A, params, exec_=None, work=None, stream=None, check=True, timeout_s=
         work = Workspace(M, N, params, device=A.device, f32=f32)
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
     fn = _lib.factor_f32_ptr if f32 else _lib.factor_ptr
-    fn(A.data_ptr(), M, N, lda, params, exec_, work.ptr, work.bytes, s.cuda_stream)
+    fac = fn(A.data_ptr(), M, N, lda, params, exec_, work.ptr, work.bytes, s.cuda_stream, handle=handle)
     if check:
         st, info = _lib.status(work.ptr, s.cuda_stream, timeout_s=timeout_s, detail=True)
         if st != 0:
             err = HQRError("hqr_factor (device)", st)
             err.detail = info
             raise RuntimeError("%s; task %d waited on counter %d for %d, last saw %d" % ((err,) + tuple(info)))
-    return work
+    return (work, fac) if handle else work
 
 
 def _apply(trans, B, M, N, params, work, exec_, bwork, stream, check):
@@ -159,11 +161,12 @@ def solve(B, M, N, params, work, exec_=None, bwork=None, stream=None, check=True
     return bwork
 
 
-def lstsq(A, B, params, exec_=None, work=None, stream=None, check=True):
+def lstsq(A, B, params, exec_=None, work=None, stream=None, check=True, handle=False):
     """Least squares min ||A X - B|| in place: A (M x N) is overwritten by its
     factorization, B (M x nrhs) by X in its first N rows and the residual
     components of Q^T B below.  Returns the workspace (it also holds the
-    factors for :func:`apply_qt`)."""
+    factors for :func:`apply_qt`), or (workspace, :class:`Factors`) with
+    ``handle``."""
     import torch
 
     M, N, lda = _colmajor_args(A, "A")
@@ -173,11 +176,44 @@ def lstsq(A, B, params, exec_=None, work=None, stream=None, check=True):
     if work is None:
         work = Workspace(M, N, params, device=A.device, nrhs=nrhs)
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
-    _lib.lstsq_ptr(A.data_ptr(), M, N, lda, B.data_ptr(), ldb, nrhs, params, exec_, work.ptr, work.bytes,
-                   s.cuda_stream)
+    fac = _lib.lstsq_ptr(A.data_ptr(), M, N, lda, B.data_ptr(), ldb, nrhs, params, exec_, work.ptr, work.bytes,
+                         s.cuda_stream, handle=handle)
     if check:
         _device_status(work, s, "hqr_lstsq")
-    return work
+    return (work, fac) if handle else work
+
+
+class _Buf:
+    """A device byte buffer with the ``ptr``/``bytes`` of a workspace."""
+
+    def __init__(self, nbytes, device):
+        import torch
+
+        self.bytes = nbytes
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self):
+        return self.buf.data_ptr()
+
+
+def factors_run(fac, op, B, exec_=None, bwork=None, stream=None, check=True):
+    """B <- Q^T B (op "apply_qt"), Q B ("apply_q") or the least-squares
+    solution ("solve") with the factorization of the handle ``fac``
+    (hqr_factors_*); B is a column-major float64 CUDA tensor with M rows."""
+    import torch
+
+    M = fac.query()[0]
+    MB, nrhs, ldb = _colmajor_args(B, "B")
+    if MB != M:
+        raise ValueError("B must have M = %d rows" % M)
+    if bwork is None:
+        bwork = _Buf(fac.apply_workspace_size(nrhs), B.device)
+    s = stream if stream is not None else torch.cuda.current_stream(B.device)
+    getattr(fac, op)(B.data_ptr(), ldb, nrhs, bwork.ptr, bwork.bytes, s.cuda_stream, exec_)
+    if check:
+        _device_status(bwork, s, "hqr_factors_" + op)
+    return bwork
 
 
 def lstsq_ir(A, b, params, exec_=None, max_iter=30, tol=1e-12, stream=None, residual=False):

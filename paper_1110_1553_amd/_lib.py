@@ -19,14 +19,18 @@ OPS = ("GEQRT", "UNMQR", "TSQRT", "TSMQR", "TTQRT", "TTMQR")
 ERR_WATCHDOG = 2
 ERR_TIMEOUT = 7
 ERR_SINGULAR = 8
+ERR_FACTORS = 9
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}
 
 
 class Params(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in ("nb", "ib", "p", "a", "low", "high", "coupling", "domino")]
+    _fields_ = [(n, ctypes.c_int32) for n in ("nb", "ib", "p", "a", "low", "high", "coupling", "domino", "precision")]
 
 
 class Exec(ctypes.Structure):
-    _fields_ = [("workers", ctypes.c_int32), ("order", ctypes.c_int32), ("spin_limit", ctypes.c_int64)]
+    _fields_ = [("workers", ctypes.c_int32), ("order", ctypes.c_int32), ("spin_limit", ctypes.c_int64),
+                ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p)]
 
 
 class Elim(ctypes.Structure):
@@ -52,7 +56,9 @@ EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_s
            "hqr_status", "hqr_status_ex", "hqr_release_plans", "hqr_strerror", "hqr_last_error", "hqr_timeline", "hqr_version",
            "hqr_batch_create", "hqr_batch_workspace_size", "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run",
            "hqr_batch_status", "hqr_batch_publish_status", "hqr_batch_destroy", "hqr_lstsq_batched",
-           "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors", "hqr_batch_export_all")
+           "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors", "hqr_batch_export_all",
+           "hqr_factors_apply_workspace_size", "hqr_factors_apply_qt", "hqr_factors_apply_q", "hqr_factors_solve",
+           "hqr_factors_query", "hqr_factors_destroy")
 
 _lib = None
 
@@ -78,9 +84,9 @@ def load():
     lib.hqr_dag_stats.argtypes = [i32, i32, P(Params), P(DagInfo)]
     lib.hqr_plan_tasks.argtypes = [i32, i32, P(Params), i32, vp, i64, P(i64)]
     lib.hqr_workspace_size.argtypes = [i64, i64, P(Params), P(ctypes.c_size_t)]
-    lib.hqr_factor.argtypes = [vp, i64, i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
+    lib.hqr_factor.argtypes = [vp, i64, i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp, P(vp)]
     lib.hqr_workspace_size_f32.argtypes = [i64, i64, P(Params), P(ctypes.c_size_t)]
-    lib.hqr_factor_f32.argtypes = [vp, i64, i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
+    lib.hqr_factor_f32.argtypes = [vp, i64, i64, i64, P(Params), P(Exec), vp, ctypes.c_size_t, vp, P(vp)]
     lib.hqr_apply_workspace_size.argtypes = [i64, i32, P(Params), P(ctypes.c_size_t)]
     lib.hqr_lstsq_ir_workspace_size.argtypes = [i64, i64, P(Params), P(ctypes.c_size_t)]
     lib.hqr_lstsq_ir.argtypes = [vp, i64, i64, i64, vp, vp, vp, P(Params), P(Exec), i32, ctypes.c_double, vp,
@@ -91,7 +97,15 @@ def load():
     lib.hqr_batch_export_factors.argtypes = [vp, i32, vp, vp, ctypes.c_size_t, vp]
     lib.hqr_apply_q.argtypes = apply_args
     lib.hqr_lstsq_workspace_size.argtypes = [i64, i64, i32, P(Params), P(ctypes.c_size_t)]
-    lib.hqr_lstsq.argtypes = [vp, i64, i64, i64, vp, i64, i32, P(Params), P(Exec), vp, ctypes.c_size_t, vp]
+    lib.hqr_lstsq.argtypes = [vp, i64, i64, i64, vp, i64, i32, P(Params), P(Exec), vp, ctypes.c_size_t, vp, P(vp)]
+    lib.hqr_factors_apply_workspace_size.argtypes = [vp, i32, P(ctypes.c_size_t)]
+    handle_args = [vp, P(Exec), vp, i64, i32, vp, ctypes.c_size_t, vp]
+    lib.hqr_factors_apply_qt.argtypes = handle_args
+    lib.hqr_factors_apply_q.argtypes = handle_args
+    lib.hqr_factors_solve.argtypes = handle_args
+    lib.hqr_factors_query.argtypes = [vp, P(i64), P(i64), P(Params), P(vp), P(ctypes.c_size_t)]
+    lib.hqr_factors_destroy.argtypes = [vp]
+    lib.hqr_factors_destroy.restype = None
     lib.hqr_batch_create.argtypes = [i32, vp, vp, vp, P(Params), P(Exec), P(vp)]
     lib.hqr_batch_workspace_size.argtypes = [vp, P(ctypes.c_size_t)]
     lib.hqr_batch_num_tasks.argtypes = [vp, vp, vp, i64, P(i64)]
@@ -122,7 +136,9 @@ def load():
                  "hqr_lstsq_ir_workspace_size", "hqr_lstsq_ir", "hqr_batch_create", "hqr_batch_workspace_size",
                  "hqr_batch_num_tasks", "hqr_batch_bind", "hqr_batch_run", "hqr_batch_status", "hqr_batch_publish_status",
                  "hqr_lstsq_batched",
-                 "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors", "hqr_batch_export_all"):
+                 "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors", "hqr_batch_export_all",
+                 "hqr_factors_apply_workspace_size", "hqr_factors_apply_qt", "hqr_factors_apply_q",
+                 "hqr_factors_solve", "hqr_factors_query"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -141,13 +157,17 @@ def _check(fn, rc):
         raise HQRError(fn, rc)
 
 
-def make_params(nb=256, p=1, a=1, low="greedy", high="flat", coupling="chain", domino=0, ib=16) -> Params:
+def make_params(nb=256, p=1, a=1, low="greedy", high="flat", coupling="chain", domino=0, ib=16,
+                precision="fp64") -> Params:
     t = lambda x: TREES[x] if isinstance(x, str) else int(x)  # noqa: E731
-    return Params(nb, ib, p, a, t(low), t(high), t(coupling), int(domino))
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return Params(nb, ib, p, a, t(low), t(high), t(coupling), int(domino), prec)
 
 
-def make_exec(workers=0, order=0, spin_limit=0) -> Exec:
-    return Exec(workers, order, spin_limit)
+def make_exec(workers=0, order=0, spin_limit=0, ev_begin=None, ev_end=None) -> Exec:
+    """Execution controls; ev_begin / ev_end are raw hipEvent_t handles (int) recorded around the
+    persistent launch of a factorization."""
+    return Exec(workers, order, spin_limit, ev_begin, ev_end)
 
 
 def elimlist(mt: int, nt: int, params: Params) -> np.ndarray:
@@ -192,11 +212,15 @@ def workspace_size(M: int, N: int, params: Params) -> int:
 
 
 def factor_ptr(dA: int, M: int, N: int, lda: int, params: Params, exec_: Exec, dwork: int, work_bytes: int,
-               stream: int) -> None:
+               stream: int, handle: bool = False):
+    """hqr_factor; with ``handle`` returns a :class:`Factors` of the result."""
+    h = ctypes.c_void_p()
     rc = load().hqr_factor(ctypes.c_void_p(dA), M, N, lda, ctypes.byref(params),
                            ctypes.byref(exec_) if exec_ is not None else None,
-                           ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(stream))
+                           ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(stream),
+                           ctypes.byref(h) if handle else None)
     _check("hqr_factor", rc)
+    return Factors(h) if handle else None
 
 
 def workspace_size_f32(M: int, N: int, params: Params) -> int:
@@ -206,11 +230,14 @@ def workspace_size_f32(M: int, N: int, params: Params) -> int:
 
 
 def factor_f32_ptr(dA: int, M: int, N: int, lda: int, params: Params, exec_: Exec, dwork: int, work_bytes: int,
-                   stream: int) -> None:
+                   stream: int, handle: bool = False):
+    h = ctypes.c_void_p()
     rc = load().hqr_factor_f32(ctypes.c_void_p(dA), M, N, lda, ctypes.byref(params),
                                ctypes.byref(exec_) if exec_ is not None else None,
-                               ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(stream))
+                               ctypes.c_void_p(dwork), work_bytes, ctypes.c_void_p(stream),
+                               ctypes.byref(h) if handle else None)
     _check("hqr_factor_f32", rc)
+    return Factors(h) if handle else None
 
 
 def lstsq_ir_workspace_size(M: int, N: int, params: Params) -> int:
@@ -262,11 +289,60 @@ def lstsq_workspace_size(M: int, N: int, nrhs: int, params: Params) -> int:
 
 
 def lstsq_ptr(dA: int, M: int, N: int, lda: int, dB: int, ldb: int, nrhs: int, params: Params, exec_: Exec,
-              dwork: int, work_bytes: int, stream: int) -> None:
+              dwork: int, work_bytes: int, stream: int, handle: bool = False):
+    h = ctypes.c_void_p()
     rc = load().hqr_lstsq(ctypes.c_void_p(dA), M, N, lda, ctypes.c_void_p(dB), ldb, nrhs, ctypes.byref(params),
                           ctypes.byref(exec_) if exec_ is not None else None, ctypes.c_void_p(dwork), work_bytes,
-                          ctypes.c_void_p(stream))
+                          ctypes.c_void_p(stream), ctypes.byref(h) if handle else None)
     _check("hqr_lstsq", rc)
+    return Factors(h) if handle else None
+
+
+class Factors:
+    """An hqr_factors handle (shape, parameters and workspace of a finished
+    factorization); freed with the object."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self.handle = handle
+
+    def query(self):
+        """(M, N, params, dwork pointer, workspace bytes)."""
+        M, N, w, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_void_p(), ctypes.c_size_t()
+        prm = Params()
+        _check("hqr_factors_query", load().hqr_factors_query(self.handle, ctypes.byref(M), ctypes.byref(N),
+                                                             ctypes.byref(prm), ctypes.byref(w), ctypes.byref(n)))
+        return M.value, N.value, prm, w.value or 0, n.value
+
+    def apply_workspace_size(self, nrhs: int) -> int:
+        n = ctypes.c_size_t()
+        _check("hqr_factors_apply_workspace_size",
+               load().hqr_factors_apply_workspace_size(self.handle, nrhs, ctypes.byref(n)))
+        return n.value
+
+    def _run(self, name, exec_, dB, ldb, nrhs, bwork, bwork_bytes, stream):
+        fn = getattr(load(), name)
+        _check(name, fn(self.handle, ctypes.byref(exec_) if exec_ is not None else None, ctypes.c_void_p(dB), ldb,
+                        nrhs, ctypes.c_void_p(bwork), bwork_bytes, ctypes.c_void_p(stream)))
+
+    def apply_qt(self, dB, ldb, nrhs, bwork, bwork_bytes, stream, exec_=None):
+        self._run("hqr_factors_apply_qt", exec_, dB, ldb, nrhs, bwork, bwork_bytes, stream)
+
+    def apply_q(self, dB, ldb, nrhs, bwork, bwork_bytes, stream, exec_=None):
+        self._run("hqr_factors_apply_q", exec_, dB, ldb, nrhs, bwork, bwork_bytes, stream)
+
+    def solve(self, dB, ldb, nrhs, bwork, bwork_bytes, stream, exec_=None):
+        self._run("hqr_factors_solve", exec_, dB, ldb, nrhs, bwork, bwork_bytes, stream)
+
+    def close(self) -> None:
+        if self.handle:
+            load().hqr_factors_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def status(dwork: int, stream: int, timeout_s: float = 0.0, detail: bool = False):

@@ -123,7 +123,7 @@ int run_apply(int trans, int64_t M, int64_t N, const hqr_params& p, const hqr_ex
   if (L.mt > 65535 || L.nt > 65535 || AL.nbc > 65535) return -2;
   if (work_bytes < L.total) return -7;
   if (bwork_bytes < AL.total) return -12;
-  hqr_exec ex{0, 0, 0};
+  hqr_exec ex{0, 0, 0, nullptr, nullptr};
   if (exec) ex = *exec;
   DevicePlan* dp = nullptr;
   int rc = get_plan(L.mt, L.nt, p, 2 + trans, &dp, AL.nbc);
@@ -149,6 +149,9 @@ int run_apply(int trans, int64_t M, int64_t N, const hqr_params& p, const hqr_ex
   if ((rc = launch_tile_copy(dB, 0, ldb, a.B, f32, M, nrhs, p.nb, 64, AL.mt, AL.nbc, true, stream))) return rc;
   const int64_t nwords = (int64_t)((AL.blocks - AL.ctrl) / sizeof(int32_t));  // ctrl + counters
   if ((rc = launch_zero_i32(a.ctrl, nwords, stream))) return rc;
+  // a workspace that holds another factorization (or none) stops the launch
+  // before its first task
+  if ((rc = launch_check_sig((const int32_t*)(w + L.ctrl), factor_sig(L, p, es), a.ctrl, stream))) return rc;
   if (a.ntasks > 0) {
     int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb, f32);
     if ((rc = launch_persistent(p.nb, a, workers, stream, f32))) return rc;
@@ -162,7 +165,7 @@ int check_apply_args(int64_t M, int64_t N, const hqr_params* params, const void*
                      int64_t ldb, int32_t nrhs, const void* bwork) {
   if (M < 1 || M < N) return -2;
   if (N < 1) return -3;
-  if (!params || check_params(*params)) return -4;
+  if (!params || check_params(*params) || params->precision != HQR_PREC_FP64) return -4;
   if (!dwork) return -6;
   if (!dB) return -8;
   if (ldb < M) return -9;
@@ -210,16 +213,69 @@ int run_factor(void* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& p,
   void* Bt = (char*)a.A + (size_t)L.mt * L.nt * p.nb * p.nb * es;
   if (nrhs > 0 && (rc = launch_tile_copy(dB, 0, ldb, Bt, f32, M, nrhs, p.nb, p.nb, L.mt, L.nrt, true, stream)))
     return rc;
-  const int64_t nwords = (int64_t)((L.tg - L.ctrl) / sizeof(int32_t));  // ctrl + counters
-  if ((rc = launch_zero_i32(a.ctrl, nwords, stream))) return rc;
+  const int64_t ncnt = (int64_t)L.mt * (L.nt + L.nrt) * L.chunks;
+  if ((rc = launch_init_ctrl(a.ctrl, factor_sig(L, p, es), a.cnt, ncnt, stream))) return rc;
   int workers = ex.workers > 0 ? ex.workers : default_workers(p.nb, f32);
+  if (ex.ev_begin && (rc = record_hip(hipEventRecord((hipEvent_t)ex.ev_begin, (hipStream_t)stream),
+                                      "hipEventRecord(ev_begin)")))
+    return rc;
   if ((rc = launch_persistent(p.nb, a, workers, stream, f32))) return rc;
+  if (ex.ev_end && (rc = record_hip(hipEventRecord((hipEvent_t)ex.ev_end, (hipStream_t)stream),
+                                    "hipEventRecord(ev_end)")))
+    return rc;
   if (copy_a_out &&
       (rc = launch_tile_copy(dA, a_f32, lda, a.A, f32, M, N, p.nb, p.nb, L.mt, L.nt, false, stream)))
     return rc;
   return 0;
 }
 
+}  // namespace hqr
+
+// Host record of a finished factorization (include/hqr.h).
+struct hqr_factors {
+  int64_t M = 0, N = 0;
+  hqr_params p{};
+  bool f32 = false;
+  const void* dwork = nullptr;
+  size_t work_bytes = 0;
+};
+
+namespace hqr {
+namespace {
+
+int make_handle(int64_t M, int64_t N, const hqr_params& p, bool f32, const void* dwork, size_t work_bytes,
+                hqr_factors** out) {
+  if (!out) return 0;
+  hqr_factors* f = new (std::nothrow) hqr_factors();
+  if (!f) return HQR_ERR_NOMEM;
+  f->M = M;
+  f->N = N;
+  f->p = p;
+  f->f32 = f32;
+  f->dwork = dwork;
+  f->work_bytes = work_bytes;
+  *out = f;
+  return 0;
+}
+
+int check_handle_args(const hqr_factors* f, const double* dB, int64_t ldb, int32_t nrhs, const void* bwork) {
+  if (!f) return -1;
+  if (!dB) return -3;
+  if (ldb < f->M) return -4;
+  if (nrhs < 1) return -5;
+  if (!bwork) return -6;
+  return 0;
+}
+
+// run_apply's argument codes (-7: dwork too small, -12: bwork too small) in
+// the numbering of the handle entry points.
+int map_apply_rc(int rc) {
+  if (rc == -12) return -7;
+  if (rc == -7 || rc == -2) return HQR_ERR_INTERNAL;  // the handle's own workspace and shape were accepted before
+  return rc;
+}
+
+}  // namespace
 }  // namespace hqr
 
 using namespace hqr;
@@ -296,20 +352,22 @@ int hqr_workspace_size(int64_t M, int64_t N, const hqr_params* params, size_t* b
 }
 
 int hqr_factor(double* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params, const hqr_exec* exec,
-               void* dwork, size_t work_bytes, void* stream) {
+               void* dwork, size_t work_bytes, void* stream, hqr_factors** out) {
   if (!dA) return -1;
   if (M < 1 || M < N) return -2;
   if (N < 1) return -3;
   if (lda < M) return -4;
-  if (!params || check_params(*params)) return -5;
+  if (!params || check_params(*params) || params->precision != HQR_PREC_FP64) return -5;
   if (!dwork) return -7;
   const Layout L = layout_for(M, N, *params);
   if (L.mt > 65535 || L.nt > 65535) return -2;
   if (work_bytes < L.total) return -8;
-  hqr_exec ex{0, 0, 0};
+  hqr_exec ex{0, 0, 0, nullptr, nullptr};
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -6;
-  return run_factor(dA, M, N, lda, *params, ex, dwork, nullptr, 0, 0, stream, true, false, false);
+  int rc = run_factor(dA, M, N, lda, *params, ex, dwork, nullptr, 0, 0, stream, true, false, false);
+  if (rc) return rc;
+  return make_handle(M, N, *params, false, dwork, work_bytes, out);
 }
 
 int hqr_workspace_size_f32(int64_t M, int64_t N, const hqr_params* params, size_t* bytes) {
@@ -322,20 +380,25 @@ int hqr_workspace_size_f32(int64_t M, int64_t N, const hqr_params* params, size_
 }
 
 int hqr_factor_f32(float* dA, int64_t M, int64_t N, int64_t lda, const hqr_params* params, const hqr_exec* exec,
-                   void* dwork, size_t work_bytes, void* stream) {
+                   void* dwork, size_t work_bytes, void* stream, hqr_factors** out) {
   if (!dA) return -1;
   if (M < 1 || M < N) return -2;
   if (N < 1) return -3;
   if (lda < M) return -4;
   if (!params || check_params(*params)) return -5;
+  hqr_params p = *params;
+  if (p.precision == HQR_PREC_FP64) p.precision = HQR_PREC_FP32;
+  if (p.precision == HQR_PREC_BF16) return -5;  // BF16 products: not built
   if (!dwork) return -7;
-  const Layout L = layout_for(M, N, *params, 0, sizeof(float));
+  const Layout L = layout_for(M, N, p, 0, sizeof(float));
   if (L.mt > 65535 || L.nt > 65535) return -2;
   if (work_bytes < L.total) return -8;
-  hqr_exec ex{0, 0, 0};
+  hqr_exec ex{0, 0, 0, nullptr, nullptr};
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -6;
-  return run_factor(dA, M, N, lda, *params, ex, dwork, nullptr, 0, 0, stream, true, true, true);
+  int rc = run_factor(dA, M, N, lda, p, ex, dwork, nullptr, 0, 0, stream, true, true, true);
+  if (rc) return rc;
+  return make_handle(M, N, p, true, dwork, work_bytes, out);
 }
 
 int hqr_apply_workspace_size(int64_t M, int32_t nrhs, const hqr_params* params, size_t* bytes) {
@@ -372,7 +435,8 @@ int hqr_lstsq_workspace_size(int64_t M, int64_t N, int32_t nrhs, const hqr_param
 }
 
 int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t ldb, int32_t nrhs,
-              const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream) {
+              const hqr_params* params, const hqr_exec* exec, void* dwork, size_t work_bytes, void* stream,
+              hqr_factors** out) {
   if (!dA) return -1;
   if (M < 1 || M < N) return -2;
   if (N < 1) return -3;
@@ -380,13 +444,13 @@ int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t
   if (!dB) return -5;
   if (ldb < M) return -6;
   if (nrhs < 1) return -7;
-  if (!params || check_params(*params)) return -8;
+  if (!params || check_params(*params) || params->precision != HQR_PREC_FP64) return -8;
   if (!dwork) return -10;
   const hqr_params& p = *params;
   const Layout L = layout_for(M, N, p, nrhs);
   if (L.mt > 65535 || L.nt + L.nrt > 65535) return -2;
   if (work_bytes < L.total) return -11;
-  hqr_exec ex{0, 0, 0};
+  hqr_exec ex{0, 0, 0, nullptr, nullptr};
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -9;
   int rc = run_factor(dA, M, N, lda, p, ex, dwork, dB, ldb, nrhs, stream, true, false, false);
@@ -396,7 +460,8 @@ int hqr_lstsq(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t
   double* Bt = (double*)(w + L.tiles) + (size_t)L.mt * L.nt * p.nb * p.nb;
   // the right-hand sides are tile columns of nb after the matrix tiles
   if ((rc = launch_trsv(p.nb, tiles, Bt, p.nb, (int32_t*)(w + L.ctrl), N, L.mt, nrhs, stream))) return rc;
-  return launch_tile_copy(dB, ldb, Bt, M, nrhs, p.nb, p.nb, L.mt, L.nrt, false, stream);
+  if ((rc = launch_tile_copy(dB, ldb, Bt, M, nrhs, p.nb, p.nb, L.mt, L.nrt, false, stream))) return rc;
+  return make_handle(M, N, p, false, dwork, work_bytes, out);
 }
 
 int hqr_solve(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* exec, const void* dwork,
@@ -415,6 +480,49 @@ int hqr_solve(int64_t M, int64_t N, const hqr_params* params, const hqr_exec* ex
   if ((rc = launch_trsv(p.nb, tiles, Bb, 64, (int32_t*)(bw + AL.ctrl), N, L.mt, nrhs, stream))) return rc;
   return launch_tile_copy(dB, ldb, Bb, M, nrhs, p.nb, 64, AL.mt, AL.nbc, false, stream);
 }
+
+int hqr_factors_apply_workspace_size(const hqr_factors* f, int32_t nrhs, size_t* bytes) {
+  if (!f) return -1;
+  if (nrhs < 1) return -2;
+  if (!bytes) return -3;
+  *bytes = apply_layout_for(f->M, nrhs, f->p, f->f32 ? sizeof(float) : sizeof(double)).total;
+  return 0;
+}
+
+int hqr_factors_apply_qt(const hqr_factors* f, const hqr_exec* exec, double* dB, int64_t ldb, int32_t nrhs,
+                         void* bwork, size_t bwork_bytes, void* stream) {
+  if (int rc = check_handle_args(f, dB, ldb, nrhs, bwork)) return rc;
+  return map_apply_rc(run_apply(1, f->M, f->N, f->p, exec, f->dwork, f->work_bytes, dB, ldb, nrhs, bwork,
+                                bwork_bytes, stream, true, f->f32));
+}
+
+int hqr_factors_apply_q(const hqr_factors* f, const hqr_exec* exec, double* dB, int64_t ldb, int32_t nrhs,
+                        void* bwork, size_t bwork_bytes, void* stream) {
+  if (int rc = check_handle_args(f, dB, ldb, nrhs, bwork)) return rc;
+  return map_apply_rc(run_apply(0, f->M, f->N, f->p, exec, f->dwork, f->work_bytes, dB, ldb, nrhs, bwork,
+                                bwork_bytes, stream, true, f->f32));
+}
+
+int hqr_factors_solve(const hqr_factors* f, const hqr_exec* exec, double* dB, int64_t ldb, int32_t nrhs,
+                      void* bwork, size_t bwork_bytes, void* stream) {
+  if (int rc = check_handle_args(f, dB, ldb, nrhs, bwork)) return rc;
+  if (f->f32) return -1;
+  return map_apply_rc(hqr_solve(f->M, f->N, &f->p, exec, f->dwork, f->work_bytes, dB, ldb, nrhs, bwork,
+                                bwork_bytes, stream));
+}
+
+int hqr_factors_query(const hqr_factors* f, int64_t* M, int64_t* N, hqr_params* params, const void** dwork,
+                      size_t* work_bytes) {
+  if (!f) return -1;
+  if (M) *M = f->M;
+  if (N) *N = f->N;
+  if (params) *params = f->p;
+  if (dwork) *dwork = f->dwork;
+  if (work_bytes) *work_bytes = f->work_bytes;
+  return 0;
+}
+
+void hqr_factors_destroy(hqr_factors* f) { delete f; }
 
 int hqr_status(const void* dwork, void* stream, int32_t* status) {
   return hqr_status_ex(dwork, stream, 0.0, status, nullptr);
@@ -487,6 +595,7 @@ const char* hqr_strerror(int code) {
     case HQR_ERR_INVALID_LIST: return "elimination list breaks the validity rules";
     case HQR_ERR_TIMEOUT: return "the GPU work did not finish within the time limit";
     case HQR_ERR_SINGULAR: return "R has a zero diagonal entry (A is rank deficient)";
+    case HQR_ERR_FACTORS: return "the workspace does not hold the factorization the arguments describe";
     default: return "unknown error";
   }
 }

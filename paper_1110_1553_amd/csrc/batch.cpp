@@ -39,10 +39,11 @@ namespace hqr {
 // region is 256-byte aligned and a multiple of 16 bytes long.
 struct ExportDesc {
   char* dst;          // destination workspace, null: the problem is skipped
-  int64_t zero_bytes; // control words and counters at its start, cleared
+  int64_t zero_bytes; // control words at its start, cleared (the signature words set to `sig`)
   int64_t tg_dst, tk_dst, tiles_dst;
   int64_t tg_src, tk_src, tiles_src;  // in the batch workspace
   int64_t tsz, asz;   // bytes of each T array, of the matrix tiles
+  FactorSig sig;      // signature of the factorization (control words kSigWord..)
 };
 }  // namespace hqr
 
@@ -166,6 +167,11 @@ static __global__ void export_batched_kernel(const hqr::ExportDesc* e, const cha
     char* o;
     if (x < z) {
       o = d.dst + 16 * x;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t word = 4 * x + k;
+        if (word >= hqr::kSigWord && word < hqr::kSigWord + hqr::kSigWords) v[k] = (unsigned)d.sig.w[word - hqr::kSigWord];
+      }
     } else if (x < z + t) {
       v = ((const u4v*)(w + d.tg_src))[x - z];
       o = d.dst + d.tg_dst + 16 * (x - z);
@@ -187,8 +193,8 @@ int hqr_batch_create(int32_t count, const int64_t* M, const int64_t* N, const in
   if (count < 1 || count > 65535) return -1;
   if (!M) return -2;
   if (!N) return -3;
-  if (!params || check_params(*params)) return -5;
-  hqr_exec ex{0, 0, 0};
+  if (!params || check_params(*params) || params->precision != HQR_PREC_FP64) return -5;
+  hqr_exec ex{0, 0, 0, nullptr, nullptr};
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -6;
   if (!out) return -7;
@@ -367,7 +373,13 @@ int hqr_batch_run(const hqr_batch* b, void* dwork, size_t work_bytes, void* stre
     a.lda = nb;
     // per-problem fields (A, Tg, Tk, cnt, mt, nt, cnt_cols) are set per task
     const int workers = b->ex.workers > 0 ? b->ex.workers : default_workers(nb);
+    if (b->ex.ev_begin && record_hip(hipEventRecord((hipEvent_t)b->ex.ev_begin, (hipStream_t)stream),
+                                     "hipEventRecord(ev_begin)"))
+      return HQR_ERR_HIP;
     if (int rc = launch_persistent(nb, a, workers, stream)) return rc;
+    if (b->ex.ev_end && record_hip(hipEventRecord((hipEvent_t)b->ex.ev_end, (hipStream_t)stream),
+                                   "hipEventRecord(ev_end)"))
+      return HQR_ERR_HIP;
   }
   if (b->max_nrhs > 0) {
     if (int rc = launch_trsv_batched(nb, d, w, (int32_t*)w, (int32_t*)(w + b->off_info), b->count, b->max_nrhs,
@@ -433,8 +445,9 @@ int hqr_batch_export_factors(const hqr_batch* b, int32_t q, const void* dwork, v
   hipStream_t s = (hipStream_t)stream;
   const size_t tsz = (size_t)L.mt * L.nt * b->p.nb * 16 * sizeof(double);
   const size_t asz = (size_t)L.mt * L.nt * b->p.nb * b->p.nb * sizeof(double);
-  // control words and counters of the copy start at zero (a status read finds no error)
-  if (int rc = launch_zero_i32((int32_t*)o, (int64_t)(L.tg / sizeof(int32_t)), stream)) return rc;
+  // control words of the copy start at zero (a status read finds no error), with the signature of the
+  // factorization for the apply entry points
+  if (int rc = launch_init_ctrl((int32_t*)o, factor_sig(L, b->p, sizeof(double)), nullptr, 0, stream)) return rc;
   if (int rc = record_hip(hipMemcpyAsync(o + L.tg, w + d.tg, tsz, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(Tg)"))
     return rc;
   if (int rc = record_hip(hipMemcpyAsync(o + L.tk, w + d.tk, tsz, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(Tk)"))
@@ -459,6 +472,7 @@ int hqr_batch_export_all(const hqr_batch* b, void* dwork, void* const* dst, cons
     const ProbDesc& d = b->desc[q];
     x.dst = (char*)dst[q];
     x.zero_bytes = (int64_t)L.tg;
+    x.sig = factor_sig(L, b->p, sizeof(double));
     x.tg_dst = (int64_t)L.tg;
     x.tk_dst = (int64_t)L.tk;
     x.tiles_dst = (int64_t)L.tiles;

@@ -578,6 +578,10 @@ __device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
     for (int l = 0; l < 16; ++l)
       if (l == k) trow[l] = val;
   };
+  // kept as a loop: unrolled, the sixteen column steps of each panel kind
+  // take tens of KB of code and the panel tasks miss in the instruction
+  // cache that a compute unit pair shares
+#pragma unroll 1
   for (int jj = 0; jj < 16; ++jj) {
     E* vb = Vb + (jj & 1) * NB;
     if (cc == jj) {
@@ -1281,6 +1285,21 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
     p[x] = 0;
 }
 
+__global__ void init_ctrl_kernel(int32_t* ctrl, FactorSig sig, int32_t* cnt, int64_t ncnt) {
+  const int64_t x0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x0 < kCtrlWords) {
+    const int w = (int)x0;
+    ctrl[w] = (w >= kSigWord && w < kSigWord + kSigWords) ? sig.w[w - kSigWord] : 0;
+  }
+  for (int64_t x = x0; x < ncnt; x += (int64_t)gridDim.x * blockDim.x) cnt[x] = 0;
+}
+
+__global__ void check_sig_kernel(const int32_t* fctrl, FactorSig sig, int32_t* bctrl) {
+  const int w = threadIdx.x;
+  const bool bad = w < kSigWords && fctrl[kSigWord + w] != sig.w[w];
+  if (__any(bad) && w == 0) bctrl[1] = HQR_ERR_FACTORS;
+}
+
 // Column-major M x N matrix (leading dimension lda) <-> blocks of nb rows
 // x tw columns (block (i, j) at index j * mt + i, column-major inside with
 // leading dimension nb; tw = nb for the tiles of A, 64 for the blocks of
@@ -1676,6 +1695,17 @@ int launch_zero_i32(int32_t* p, int64_t n, void* stream) {
   if (n <= 0) return 0;
   hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, p, n);
   return record_hip(hipGetLastError(), "zero_i32_kernel launch");
+}
+
+int launch_init_ctrl(int32_t* ctrl, const FactorSig& sig, int32_t* cnt, int64_t ncnt, void* stream) {
+  const int64_t n = ncnt > kCtrlWords ? ncnt : kCtrlWords;
+  hipLaunchKernelGGL(init_ctrl_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, ctrl, sig, cnt, ncnt);
+  return record_hip(hipGetLastError(), "init_ctrl_kernel launch");
+}
+
+int launch_check_sig(const int32_t* fctrl, const FactorSig& sig, int32_t* bctrl, void* stream) {
+  hipLaunchKernelGGL(check_sig_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, fctrl, sig, bctrl);
+  return record_hip(hipGetLastError(), "check_sig_kernel launch");
 }
 
 int launch_tile_copy(void* A, int a_f32, int64_t lda, void* At, int at_f32, int64_t M, int64_t N, int nb, int tw,

@@ -14,8 +14,9 @@
 // normwise backward error of the augmented system,
 //     eta = sqrt(||f||^2 + ||g||^2) / (||A||_F (||x|| + ||r||) + ||b||),
 // evaluated before each correction; the loop stops once eta <= tol, when a
-// correction did not lower eta (the attainable accuracy is reached), or
-// after max_iter corrections.
+// correction did not lower eta (the attainable accuracy is reached; the
+// iterate before that correction is returned), or after max_iter
+// corrections.
 //
 // Workspace: the FP32 factorization (tiles and T factors), the FP32 block of
 // the Q applications, then the FP64 vectors x (N), r (M), f (M), g (N),
@@ -36,7 +37,7 @@ namespace {
 struct IrLayout {
   Layout fac;
   ApplyLayout app;
-  size_t app_off, x, r, f, g, y, norms, total;
+  size_t app_off, x, r, f, g, y, xp, rp, norms, total;
 };
 
 IrLayout ir_layout(int64_t M, int64_t N, const hqr_params& p) {
@@ -50,6 +51,8 @@ IrLayout ir_layout(int64_t M, int64_t N, const hqr_params& p) {
   L.f = off; off = align256(off + (size_t)M * sizeof(double));
   L.g = off; off = align256(off + (size_t)N * sizeof(double));
   L.y = off; off = align256(off + (size_t)N * sizeof(double));
+  L.xp = off; off = align256(off + (size_t)N * sizeof(double));
+  L.rp = off; off = align256(off + (size_t)M * sizeof(double));
   L.norms = off; off = align256(off + 4 * sizeof(double));
   L.total = off;
   return L;
@@ -81,7 +84,8 @@ int hqr_lstsq_ir(const double* dA, int64_t M, int64_t N, int64_t lda, const doub
   if (!db) return -5;
   if (!dx) return -6;
   if (!params || check_params(*params)) return -8;
-  hqr_exec ex{0, 0, 0};
+  if (params->precision == HQR_PREC_BF16) return -8;  // BF16 factors: not built
+  hqr_exec ex{0, 0, 0, nullptr, nullptr};
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -9;
   if (max_iter < 1) return -10;
@@ -98,6 +102,8 @@ int hqr_lstsq_ir(const double* dA, int64_t M, int64_t N, int64_t lda, const doub
   double* f = (double*)(w + L.f);
   double* g = (double*)(w + L.g);
   double* y = (double*)(w + L.y);
+  double* xp = (double*)(w + L.xp);  // the iterate before the last correction
+  double* rp = (double*)(w + L.rp);
   double* norms = (double*)(w + L.norms);
   double* colsq = y;  // squared column norms of A, before y is needed
   const float* Rt = (const float*)(w + L.fac.tiles);
@@ -144,8 +150,24 @@ int hqr_lstsq_ir(const double* dA, int64_t M, int64_t N, int64_t lda, const doub
       converged = true;
       break;
     }
-    if (it >= max_iter || !std::isfinite(eta) || eta >= prev) break;
+    if (it > 0 && (!std::isfinite(eta) || eta >= prev)) {
+      // the last correction did not lower eta: return the iterate before it
+      if ((rc = record_hip(hipMemcpyAsync(x, xp, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s),
+                           "hipMemcpyAsync(x restore)")) ||
+          (rc = record_hip(hipMemcpyAsync(r, rp, (size_t)M * sizeof(double), hipMemcpyDeviceToDevice, s),
+                           "hipMemcpyAsync(r restore)")))
+        return rc;
+      eta = prev;
+      --it;
+      break;
+    }
+    if (it >= max_iter || !std::isfinite(eta)) break;
     prev = eta;
+    if ((rc = record_hip(hipMemcpyAsync(xp, x, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s),
+                         "hipMemcpyAsync(x save)")) ||
+        (rc = record_hip(hipMemcpyAsync(rp, r, (size_t)M * sizeof(double), hipMemcpyDeviceToDevice, s),
+                         "hipMemcpyAsync(r save)")))
+      return rc;
     if ((rc = launch_ir_trsv(Rt, p.nb, L.fac.mt, N, g, true, stream))) return rc;       // h = R^{-T} g
     if ((rc = run_apply(1, M, N, p, &ex, dwork, work_bytes, f, M, 1, bwork, L.app.total, stream, true, true)))
       return rc;                                                                         // f = Q^T f

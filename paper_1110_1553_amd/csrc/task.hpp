@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "elim.hpp"
+#include "layout.hpp"
 
 namespace hqr {
 
@@ -56,6 +57,18 @@ constexpr int kTraceSlots = 4096;  // workgroups traced
 
 // Zero `n` int32 words on `stream` with a fill kernel.
 int launch_zero_i32(int32_t* p, int64_t n, void* stream);
+
+// Start of a factorization launch: the kCtrlWords control words are zeroed
+// except the signature words (kSigWord..), which receive `sig`, and the
+// `ncnt` dependency counters at `cnt` are zeroed (cnt may be null when
+// ncnt = 0).  One fill kernel.
+int launch_init_ctrl(int32_t* ctrl, const FactorSig& sig, int32_t* cnt, int64_t ncnt, void* stream);
+
+// Apply launches: if the signature words of the factorization workspace
+// `fctrl` differ from `sig`, sets the status word bctrl[1] of the apply
+// workspace to HQR_ERR_FACTORS, which stops the persistent launch that
+// follows before its first task.
+int launch_check_sig(const int32_t* fctrl, const FactorSig& sig, int32_t* bctrl, void* stream);
 
 // Run every task of the plan in one persistent launch of `workers`
 // workgroups.  nb is 64, 128 or 256.

@@ -175,12 +175,21 @@ class GpuBackend:
         """Least squares for new right-hand sides B (M x nrhs, column-major,
         overwritten as hqr_solve does) with the kept factorization of
         request rid; returns False if it was evicted."""
+        import torch
+
         from . import solve
 
         w = self.store.get(rid) if self.store is not None else None
         if w is None:
             return False
-        solve(B, M, N, self.params, w, self.exec_, stream=self.side)
+        # the kept workspace was allocated on a slot stream: tell the caching
+        # allocator that the side stream uses it too, so that an eviction
+        # does not hand its memory to new work while the solve still reads it;
+        # the solve's own scratch is allocated on the side stream
+        w.buf.record_stream(self.side)
+        B.record_stream(self.side)
+        with torch.cuda.stream(self.side):
+            solve(B, M, N, self.params, w, self.exec_, stream=self.side)
         return True
 
 

@@ -40,15 +40,15 @@ def test_argument_checks_do_not_touch_the_device(hqr_lib):
 
     p = h.make_params(nb=64, a=100)
     # M < N, lda < M, bad tile size, bad inner blocking: rejected before any HIP call
-    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 100, 200, 100, ctypes.byref(p), None, ctypes.c_void_p(16), 1 << 30, None) == -2
-    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 200, 100, 100, ctypes.byref(p), None, ctypes.c_void_p(16), 1 << 30, None) == -4
+    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 100, 200, 100, ctypes.byref(p), None, ctypes.c_void_p(16), 1 << 30, None, None) == -2
+    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 200, 100, 100, ctypes.byref(p), None, ctypes.c_void_p(16), 1 << 30, None, None) == -4
     bad = h.make_params(nb=96)
-    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 256, 128, 256, ctypes.byref(bad), None, ctypes.c_void_p(16), 1 << 30, None) == -5
+    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 256, 128, 256, ctypes.byref(bad), None, ctypes.c_void_p(16), 1 << 30, None, None) == -5
     bad = h.make_params(nb=64, ib=32)
-    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 256, 128, 256, ctypes.byref(bad), None, ctypes.c_void_p(16), 1 << 30, None) == -5
+    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 256, 128, 256, ctypes.byref(bad), None, ctypes.c_void_p(16), 1 << 30, None, None) == -5
     # workspace too small
     need = h.workspace_size(256, 128, p)
-    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 256, 128, 256, ctypes.byref(p), None, ctypes.c_void_p(16), need - 1, None) == -8
+    assert hqr_lib.hqr_factor(ctypes.c_void_p(16), 256, 128, 256, ctypes.byref(p), None, ctypes.c_void_p(16), need - 1, None, None) == -8
     with pytest.raises(h.HQRError):
         h.workspace_size(10, 20, p)
     assert _lib.load().hqr_strerror(2).decode().startswith("a task waited")
@@ -84,9 +84,9 @@ def test_apply_and_lstsq_argument_checks(hqr_lib):
     lneed = h.lstsq_workspace_size(256, 128, 3, p)
     assert lneed >= need + 256 * 64 * 8
     L = hqr_lib.hqr_lstsq
-    assert L(vp(16), 256, 128, 256, vp(16), 200, 1, ctypes.byref(p), None, vp(16), lneed, None) == -6
-    assert L(vp(16), 256, 128, 256, vp(16), 256, 3, ctypes.byref(p), None, vp(16), lneed - 1, None) == -11
-    assert L(vp(16), 256, 128, 256, vp(16), 256, 0, ctypes.byref(p), None, vp(16), lneed, None) == -7
+    assert L(vp(16), 256, 128, 256, vp(16), 200, 1, ctypes.byref(p), None, vp(16), lneed, None, None) == -6
+    assert L(vp(16), 256, 128, 256, vp(16), 256, 3, ctypes.byref(p), None, vp(16), lneed - 1, None, None) == -11
+    assert L(vp(16), 256, 128, 256, vp(16), 256, 0, ctypes.byref(p), None, vp(16), lneed, None, None) == -7
     with pytest.raises(h.HQRError):
         h.apply_workspace_size(256, 0, p)
 
@@ -101,9 +101,9 @@ def test_f32_ir_and_solve_argument_checks(hqr_lib):
     w64, w32 = h.workspace_size(512, 256, p), _lib.workspace_size_f32(512, 256, p)
     assert 512 * 256 * 4 < w32 < w64
     F = hqr_lib.hqr_factor_f32
-    assert F(vp(16), 100, 200, 100, ctypes.byref(p), None, vp(16), 1 << 30, None) == -2
-    assert F(vp(16), 200, 100, 150, ctypes.byref(p), None, vp(16), 1 << 30, None) == -4
-    assert F(vp(16), 512, 256, 512, ctypes.byref(p), None, vp(16), w32 - 1, None) == -8
+    assert F(vp(16), 100, 200, 100, ctypes.byref(p), None, vp(16), 1 << 30, None, None) == -2
+    assert F(vp(16), 200, 100, 150, ctypes.byref(p), None, vp(16), 1 << 30, None, None) == -4
+    assert F(vp(16), 512, 256, 512, ctypes.byref(p), None, vp(16), w32 - 1, None, None) == -8
     # refinement
     need = _lib.lstsq_ir_workspace_size(512, 256, p)
     assert need > w32
@@ -139,3 +139,45 @@ def test_f32_ir_and_solve_argument_checks(hqr_lib):
     assert X(None, vp(16), vp(16), vp(16), None) == -1
     assert X(b.handle, vp(16), vp(16), vp(16), None) == -2
     b.close()
+
+
+def test_precision_field_and_handle_argument_checks(hqr_lib):
+    import paper_1110_1553_amd as h
+    from paper_1110_1553_amd import _lib
+
+    vp = ctypes.c_void_p
+    # the double entry points take FP64 only; an unknown precision is a bad parameter set
+    p32 = h.make_params(nb=64, precision="fp32")
+    need = h.workspace_size(256, 128, h.make_params(nb=64))
+    assert hqr_lib.hqr_factor(vp(16), 256, 128, 256, ctypes.byref(p32), None, vp(16), need, None, None) == -5
+    bad = h.make_params(nb=64, precision=7)
+    assert hqr_lib.hqr_factor(vp(16), 256, 128, 256, ctypes.byref(bad), None, vp(16), need, None, None) == -5
+    with pytest.raises(h.HQRError):
+        h.workspace_size(256, 128, bad)
+    lneed = h.lstsq_workspace_size(256, 128, 1, h.make_params(nb=64))
+    assert hqr_lib.hqr_lstsq(vp(16), 256, 128, 256, vp(16), 256, 1, ctypes.byref(p32), None, vp(16), lneed, None,
+                             None) == -8
+    # the tree does not depend on the precision
+    assert (h.elimlist(8, 4, p32) == h.elimlist(8, 4, h.make_params(nb=64))).all()
+    # handle entry points: a NULL handle and argument checks before any device work
+    for name in ("hqr_factors_apply_qt", "hqr_factors_apply_q", "hqr_factors_solve"):
+        fn = getattr(hqr_lib, name)
+        assert fn(None, None, vp(16), 256, 1, vp(16), 1 << 20, None) == -1
+    n = ctypes.c_size_t()
+    assert hqr_lib.hqr_factors_apply_workspace_size(None, 1, ctypes.byref(n)) == -1
+    assert hqr_lib.hqr_factors_query(None, None, None, None, None, None) == -1
+    hqr_lib.hqr_factors_destroy(None)
+    assert _lib.load().hqr_strerror(_lib.ERR_FACTORS).decode().startswith("the workspace does not hold")
+
+
+def test_factorization_offsets_do_not_depend_on_right_hand_sides(hqr_lib):
+    # a least-squares workspace holds the T factors and tiles where the apply entry points look for
+    # them: its extra bytes (the right-hand-side tile columns and their counters) come after the
+    # factorization's regions, so the factorization workspace is a prefix of it in size
+    import paper_1110_1553_amd as h
+
+    for (M, N, nb) in ((2100, 513, 64), (2100, 513, 256), (32768, 2048, 256), (1000, 300, 128)):
+        p = h.make_params(nb=nb)
+        w0 = h.workspace_size(M, N, p)
+        for nrhs in (1, 3, 70, 300):
+            assert h.lstsq_workspace_size(M, N, nrhs, p) > w0
