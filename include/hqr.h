@@ -337,6 +337,36 @@ int hqr_factors_query(const hqr_factors* f, int64_t* M, int64_t* N, hqr_params* 
 /* Frees the handle (NULL is ignored); the workspace and dA are untouched. */
 void hqr_factors_destroy(hqr_factors* f);
 
+/* ---- Least squares without device allocation ----
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hqr_lstsq
+ * with its workspace and task plan held in a static device array of
+ * HQR_NOALLOC_SCRATCH_BYTES that the library's code object carries (each
+ * device the library runs on holds its own copy until the process ends).
+ * The call makes no hipMalloc, hipFree or other device allocation; on the
+ * first call for a shape and tree it builds the task plan in host memory,
+ * and it uploads the plan into the array whenever the previous call on the
+ * device used another one.  All calls on one device share the array and it
+ * keeps the last call's contents: calls that overlap in time on one device
+ * (two streams, or two host threads) race and give wrong results; calls
+ * ordered on one stream are safe.
+ *   dA, M, N, lda, dB, ldb, nrhs, params, exec  as for hqr_lstsq: on return
+ *           (after the stream) A holds R and V, B(0:N, :) the solutions.
+ *   dinfo   NULL, or 8 int32 of device memory that receive, after the
+ *           call's work, the status word (0, HQR_ERR_WATCHDOG or
+ *           HQR_ERR_SINGULAR) in dinfo[0] and the detail of hqr_status_ex
+ *           in dinfo[1..4].
+ * The factorization stays in the array only until the next call, so no
+ * handle is returned.  Errors: as hqr_lstsq for arguments -1 .. -9;
+ * HQR_ERR_WORKSPACE (nothing enqueued, message in hqr_last_error) when the
+ * workspace of hqr_lstsq_workspace_size plus the task plan (24 bytes per
+ * task) exceeds HQR_NOALLOC_SCRATCH_BYTES (64 MiB: 8192 x 512 or 4096 x
+ * 1024 at nb = 256 with one right-hand side fit, 16384 x 512 does not). */
+#define HQR_NOALLOC_SCRATCH_BYTES (64u << 20)
+int hqr_lstsq_noalloc(double* dA, int64_t M, int64_t N, int64_t lda, double* dB, int64_t ldb, int32_t nrhs,
+                      const hqr_params* params, const hqr_exec* exec, int32_t* dinfo, void* stream);
+
 /* ---- Mixed-precision least squares ----
  *
  * min ||A x - b|| for a double A (M x N, M >= N, full rank) and one

@@ -58,7 +58,7 @@ EXPORTS = ("hqr_elimlist", "hqr_plan_tasks", "hqr_elimlist_validate", "hqr_dag_s
            "hqr_batch_status", "hqr_batch_publish_status", "hqr_batch_destroy", "hqr_lstsq_batched",
            "hqr_lstsq_batched_workspace_size", "hqr_solve", "hqr_batch_export_factors", "hqr_batch_export_all",
            "hqr_factors_apply_workspace_size", "hqr_factors_apply_qt", "hqr_factors_apply_q", "hqr_factors_solve",
-           "hqr_factors_query", "hqr_factors_destroy")
+           "hqr_factors_query", "hqr_factors_destroy", "hqr_lstsq_noalloc")
 
 _lib = None
 
@@ -104,6 +104,8 @@ def load():
     lib.hqr_factors_apply_q.argtypes = handle_args
     lib.hqr_factors_solve.argtypes = handle_args
     lib.hqr_factors_query.argtypes = [vp, P(i64), P(i64), P(Params), P(vp), P(ctypes.c_size_t)]
+    lib.hqr_lstsq_noalloc.argtypes = [vp, i64, i64, i64, vp, i64, i32, P(Params), P(Exec), vp, vp]
+    lib.hqr_lstsq_noalloc.restype = ctypes.c_int
     lib.hqr_factors_destroy.argtypes = [vp]
     lib.hqr_factors_destroy.restype = None
     lib.hqr_batch_create.argtypes = [i32, vp, vp, vp, P(Params), P(Exec), P(vp)]
@@ -296,6 +298,18 @@ def lstsq_ptr(dA: int, M: int, N: int, lda: int, dB: int, ldb: int, nrhs: int, p
                           ctypes.c_void_p(stream), ctypes.byref(h) if handle else None)
     _check("hqr_lstsq", rc)
     return Factors(h) if handle else None
+
+
+def lstsq_noalloc_ptr(dA: int, M: int, N: int, lda: int, dB: int, ldb: int, nrhs: int, params: Params,
+                      exec_: Exec, dinfo: int, stream: int) -> int:
+    """hqr_lstsq_noalloc; returns its code (0, or an error code without raising, so that callers can
+    test the size limit)."""
+    return load().hqr_lstsq_noalloc(ctypes.c_void_p(dA), M, N, lda, ctypes.c_void_p(dB), ldb, nrhs,
+                                    ctypes.byref(params), ctypes.byref(exec_) if exec_ is not None else None,
+                                    ctypes.c_void_p(dinfo) if dinfo else None, ctypes.c_void_p(stream))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Factors:

@@ -181,27 +181,33 @@ int check_apply_args(int64_t M, int64_t N, const hqr_params* params, const void*
 // f32: the factorization runs in FP32 on float tiles; a_f32: dA holds
 // float (else double, rounded to float on the way in when f32).
 int run_factor(void* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& p, const hqr_exec& ex, void* dwork,
-               double* dB, int64_t ldb, int32_t nrhs, void* stream, bool copy_a_out, bool f32, bool a_f32) {
+               double* dB, int64_t ldb, int32_t nrhs, void* stream, bool copy_a_out, bool f32, bool a_f32,
+               const void* tasks, int64_t ntasks) {
   const size_t es = f32 ? sizeof(float) : sizeof(double);
   const Layout L = layout_for(M, N, p, nrhs, es);
-  ColumnChunks cc;
-  cc.last_a = L.last_a;
-  cc.nrhs_cols = nrhs;
-  DevicePlan* dp = nullptr;
-  int rc = get_plan(L.mt, L.nt, p, ex.order, &dp, 0, cc);
-  if (rc) return rc;
-  char* w = (char*)dwork;
+  int rc = 0;
   LaunchArgs a{};
+  if (tasks) {
+    a.tasks = (const DevTask*)tasks;
+    a.ntasks = ntasks;
+  } else {
+    ColumnChunks cc;
+    cc.last_a = L.last_a;
+    cc.nrhs_cols = nrhs;
+    DevicePlan* dp = nullptr;
+    if ((rc = get_plan(L.mt, L.nt, p, ex.order, &dp, 0, cc))) return rc;
+    a.tasks = dp->d_tasks;
+    a.ntasks = (int64_t)dp->plan.dev.size();
+    a.trace = trace_buffer();
+    a.timeline = timeline_buffer(a.ntasks);
+    if (a.trace) std::memset(a.trace, 0, 2 * kTraceSlots * sizeof(int32_t));
+  }
+  char* w = (char*)dwork;
   a.ctrl = (int32_t*)(w + L.ctrl);
   a.cnt = (int32_t*)(w + L.cnt);
   a.Tg = (double*)(w + L.tg);
   a.Tk = (double*)(w + L.tk);
-  a.tasks = dp->d_tasks;
-  a.ntasks = (int64_t)dp->plan.dev.size();
   a.spin_limit = ex.spin_limit > 0 ? ex.spin_limit : kDefaultSpinLimit;
-  a.trace = trace_buffer();
-  a.timeline = timeline_buffer(a.ntasks);
-  if (a.trace) std::memset(a.trace, 0, 2 * kTraceSlots * sizeof(int32_t));
   a.mt = L.mt;
   a.nt = L.nt;
   a.chunks = L.chunks;

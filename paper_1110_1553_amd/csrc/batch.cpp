@@ -78,6 +78,8 @@ struct HostKey {
 std::mutex g_host_mu;
 std::map<HostKey, std::unique_ptr<Plan>> g_host_plans;
 
+}  // namespace
+
 int host_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, const ColumnChunks& cc, const Plan** out) {
   HostKey key{mt, nt, p.nb, p.p, p.a, p.low, p.high, p.coupling, p.domino, order, cc.last_a, cc.nrhs_cols};
   std::lock_guard<std::mutex> lock(g_host_mu);
@@ -90,6 +92,8 @@ int host_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, const Colu
   *out = it->second.get();
   return 0;
 }
+
+namespace {
 
 // Pinned staging buffers for the uploads of hqr_batch_bind, a few per
 // device, reused round robin; a buffer is rewritten only after the copy that

@@ -101,6 +101,11 @@ struct ColumnChunks {
 int build_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, int chunks, Plan& plan,
                const ColumnChunks& cc = ColumnChunks());
 
+// Host plan of a factorization (build_plan with `order` and `cc`), built
+// once per (tile grid, params, order, active columns) and kept for the life
+// of the process in host memory only; thread-safe.
+int host_plan(int32_t mt, int32_t nt, const hqr_params& p, int order, const ColumnChunks& cc, const Plan** out);
+
 // Device plan of B <- Q^T B (trans = 1) or B <- Q B (trans = 0) for the
 // factorization of an mt x nt tile grid, on a B of mt tile rows and `nbc`
 // blocks of 64 columns.  The update tasks of the factorization (UNMQR,

@@ -1631,6 +1631,8 @@ int record_hip(hipError_t e, const char* where) {
 
 const char* last_error() { return g_last_error; }
 
+void set_last_error(const char* msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+
 static int grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 65536) g = 65536;

@@ -108,8 +108,12 @@ inline ApplyLayout apply_layout_for(int64_t M, int64_t nrhs, const hqr_params& p
 // (f32: FP32 tiles and kernels; a_f32: A holds float), copies A back when
 // copy_a_out.  run_apply: B <- Q^T B (trans) or Q B with the factorization
 // in dwork (f32: FP32 factors and B blocks; B itself stays double).
+// `tasks` / `ntasks`: a task plan already in device memory to run instead of
+// the library's cached one (then no tracing or timeline buffers either, so
+// that the call allocates nothing); null: the cached plan.
 int run_factor(void* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& p, const hqr_exec& ex, void* dwork,
-               double* dB, int64_t ldb, int32_t nrhs, void* stream, bool copy_a_out, bool f32, bool a_f32);
+               double* dB, int64_t ldb, int32_t nrhs, void* stream, bool copy_a_out, bool f32, bool a_f32,
+               const void* tasks = nullptr, int64_t ntasks = 0);
 int run_apply(int trans, int64_t M, int64_t N, const hqr_params& p, const hqr_exec* exec, const void* dwork,
               size_t work_bytes, double* dB, int64_t ldb, int32_t nrhs, void* bwork, size_t bwork_bytes,
               void* stream, bool copy_out, bool f32);

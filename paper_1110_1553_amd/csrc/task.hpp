@@ -98,6 +98,8 @@ int launch_trsv(int nb, const double* R, double* Y, int cw, int32_t* ctrl, int64
 // HQR_ERR_HIP on failure, 0 on success.
 int record_hip(hipError_t e, const char* where);
 const char* last_error();
+// Sets the message hqr_last_error() returns (this thread).
+void set_last_error(const char* msg);
 
 // Batched launches (one launch for `count` problems described by the
 // device array `d`, offsets relative to the workspace base `w`): copy the
