@@ -59,8 +59,56 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ double esqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float esqrt(float x) { return sqrtf(x); }
+// Reciprocal square root and reciprocal from the hardware estimates
+// (v_rsq, v_rcp) refined by Newton steps to the working precision.  The
+// arguments are positive normal numbers (a squared column norm and the sum
+// |alpha| + norm of a Householder step), so no range scaling is needed.
+//   rsq: g ~ sqrt(q) and h ~ 1 / (2 sqrt(q)) refined together (Goldschmidt),
+//        then one correction of g from its residual q - g^2.
+//   rcp: r <- r + r (1 - x r).
+struct SqrtPair {
+  double s, hs;  // sqrt(q) and 1 / (2 sqrt(q))
+};
+__device__ __forceinline__ SqrtPair esqrt2(double q) {
+  const double y = __builtin_amdgcn_rsq(q);
+  double g = q * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, q);
+  g = fma(d, h, g);
+  return {g, h};
+}
+__device__ __forceinline__ double ercp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+struct SqrtPairF {
+  float s, hs;
+};
+__device__ __forceinline__ SqrtPairF esqrt2(float q) {
+  const float y = __builtin_amdgcn_rsqf(q);
+  float g = q * y, h = 0.5f * y;
+  const float r = fmaf(-g, h, 0.5f);
+  g = fmaf(g, r, g);
+  h = fmaf(h, r, h);
+  const float d = fmaf(-g, g, q);
+  g = fmaf(d, h, g);
+  return {g, h};
+}
+__device__ __forceinline__ float ercp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  const float e = fmaf(-x, r, 1.0f);
+  return fmaf(r, e, r);
+}
 
 // Global-memory accessors for tile data inside the persistent launch.
 //
@@ -567,16 +615,26 @@ __device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
   E trow[16];
 #pragma unroll
   for (int l = 0; l < 16; ++l) trow[l] = E(0);
+  // Branch-free for a run-time k: every product of the sum is formed, those
+  // with l >= k are exact zeros (z(l,k) = 0 for l >= k, and trow[l] = 0
+  // until column l of T is formed); all 16 LDS reads are issued together.
   auto t_column = [&](int k) {
     const E tk = sm.tau[k];
-    E acc = E(0);
+    E z[16];
 #pragma unroll
-    for (int l = 0; l < 16; ++l)
-      if (l < k) acc += trow[l] * Zs[l * LDV + k];  // trow[l] = 0 for l < ti
+    for (int l = 0; l < 16; ++l) z[l] = Zs[l * LDV + k];
+    E a0 = E(0), a1 = E(0), a2 = E(0), a3 = E(0);
+#pragma unroll
+    for (int l = 0; l < 16; l += 4) {
+      a0 += trow[l] * z[l];
+      a1 += trow[l + 1] * z[l + 1];
+      a2 += trow[l + 2] * z[l + 2];
+      a3 += trow[l + 3] * z[l + 3];
+    }
+    const E acc = (a0 + a1) + (a2 + a3);
     const E val = (ti < k) ? -tk * acc : (ti == k ? tk : E(0));
 #pragma unroll
-    for (int l = 0; l < 16; ++l)
-      if (l == k) trow[l] = val;
+    for (int l = 0; l < 16; ++l) trow[l] = (l == k) ? val : trow[l];
   };
   // kept as a loop: unrolled, the sixteen column steps of each panel kind
   // take tens of KB of code and the panel tasks miss in the instruction
@@ -601,10 +659,15 @@ __device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
       const E ss = sum16((s0 + s1) + (s2 + s3));
       E tau = E(0), beta = alpha, scale = E(1);
       if (ss != E(0)) {
-        beta = esqrt(alpha * alpha + ss);
-        if (alpha >= E(0)) beta = -beta;
-        tau = (beta - alpha) / beta;
-        scale = E(1) / (alpha - beta);
+        // beta = -sign(alpha) n with n = sqrt(alpha^2 + ss); then
+        // tau = (beta - alpha) / beta = 1 + |alpha| / n and
+        // 1 / (alpha - beta) = sign(alpha) / (|alpha| + n)
+        const auto sq = esqrt2(fma(alpha, alpha, ss));
+        const E aa = alpha >= E(0) ? alpha : -alpha;
+        beta = alpha >= E(0) ? -sq.s : sq.s;
+        tau = fma(aa, sq.hs + sq.hs, E(1));
+        const E ri = ercp(aa + sq.s);
+        scale = alpha >= E(0) ? ri : -ri;
       }
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
@@ -623,12 +686,16 @@ __device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
     lds_barrier();
     if (tl && jj > 0) t_column(jj - 1);
     if (ct && cc != jj) {
+      // tau is read together with v (kept above the products), not after the
+      // reduction where only the update needs it
       const E tau = sm.tau[jj];
       E v[NM];
+#pragma unroll
+      for (int m = 0; m < NM; ++m) v[m] = vb[q + 16 * m];
+      __builtin_amdgcn_sched_barrier(0);
       E d0 = E(0), d1 = E(0), d2 = E(0), d3 = E(0);
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        v[m] = vb[q + 16 * m];
         if ((m & 3) == 0) d0 += v[m] * x[m];
         if ((m & 3) == 1) d1 += v[m] * x[m];
         if ((m & 3) == 2) d2 += v[m] * x[m];
