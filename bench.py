@@ -218,18 +218,22 @@ def run_lstsq(device, M=32768, N=2048, seed=4, reps=5):
     if h.status(work, stream) != 0:
         raise RuntimeError("device status %d in the least-squares workload" % h.status(work, stream))
     x = b[:N].clone()
-    r_ = b0 - A0 @ x
-    # optimality of the computed solution: ||A^T r|| / (||A||^2 ||x||) is of the order of the unit roundoff
-    # for a backward-stable solver
+    # the refined-residual measure: eta = ||A^T (b - A x)|| / (||A||_2 (||A||_2 ||x|| + ||b||)), with ||A||_2 = 1
+    # by construction (largest singular value 1)
     nA = torch.linalg.matrix_norm(A0, 2).item()
-    opt = (A0.t() @ r_).norm().item() / (nA * nA * x.norm().item())
+
+    def eta_l1(xv):
+        xv = xv.reshape(-1, 1)
+        rv = b0 - A0 @ xv
+        return (A0.t() @ rv).norm().item() / (nA * (nA * xv.norm().item() + b0.norm().item()))
+
     t = sum(times) / len(times)
     out = {"workload": "FP64 least squares %dx%d, kappa 1e6, one right-hand side, nb=256 hierarchical tree "
                        "(TS domains a=2, Greedy low, domino coupling, Fibonacci high, p=4)" % (M, N),
            "solves_per_s": 1.0 / t, "ms_per_solve": 1e3 * t,
            "gflops": (qr_flops(M, N) + 4.0 * M * N) / t / 1e9,
            "forward_error_vs_x_true": ((x - xs).norm() / xs.norm()).item(),
-           "normal_equations_residual": opt}
+           "eta": eta_l1(x)}
     # the same problem with an FP32 factorization refined in FP64 (hqr_lstsq_ir)
     # the refinement keeps TS domains of 4 tiles: at a = 2 the FP32 factors needed one correction more at
     # eta <= 1e-12 (37.1 against 35.0 ms)
@@ -250,10 +254,33 @@ def run_lstsq(device, M=32768, N=2048, seed=4, reps=5):
         out["ir"].append({
             "method": "FP32 tiled QR + FP64 augmented-system refinement, stop at backward error <= %g" % tol,
             "ms_per_solve": 1e3 * ti, "solves_per_s": 1.0 / ti, "iterations": info["iterations"],
-            "converged": info["converged"], "eta": info["eta"],
+            "converged": info["converged"], "eta_augmented": info["eta"], "eta": eta_l1(xi),
             "forward_error_vs_x_true": ((xi - xs.reshape(-1)).norm() / xs.norm()).item(),
             "difference_vs_fp64_solution": ((xi - x.reshape(-1)).norm() / x.norm()).item()})
     del A0, b0
+    torch.cuda.empty_cache()
+    # BF16 products (FP32 accumulation) under the same refinement, at three condition numbers: it converges
+    # only while kappa times the bfloat16 unit roundoff (2^-8) is well below one
+    out["bf16"] = []
+    pb = h.make_params(nb=256, p=4, a=4, low="greedy", high="fibonacci", domino=1, precision="bf16")
+    for kap in (1e2, 1e4, 1e6):
+        Ak = h.colmajor(inputs.graded_tall_device(M, N, seed, 1.0 / kap, device))
+        bk = (Ak @ xs + 1e-10 * torch.randn((M, 1), generator=g, device=device, dtype=torch.float64)).reshape(-1)
+        bk = bk.contiguous()
+        torch.cuda.synchronize(device)
+        t0 = time.perf_counter()
+        xb, info = h.lstsq_ir(Ak, bk, pb, max_iter=30, tol=1e-12, stream=stream)
+        torch.cuda.synchronize(device)
+        tb = time.perf_counter() - t0
+        xf, _ = h.lstsq_ir(Ak, bk, h.make_params(nb=256, p=4, a=4, low="greedy", high="fibonacci", domino=1),
+                           max_iter=30, tol=1e-15, stream=stream)
+        out["bf16"].append({
+            "kappa": kap, "method": "BF16 products, FP32 accumulation, FP64 refinement, stop at <= 1e-12 or 30",
+            "ms_per_solve": 1e3 * tb, "iterations": info["iterations"], "converged": info["converged"],
+            "eta_augmented": info["eta"], "eta_history": info["history"],
+            "forward_error_vs_x_true": ((xb - xs.reshape(-1)).norm() / xs.norm()).item(),
+            "difference_vs_refined_fp32_solution": ((xb - xf).norm() / xf.norm()).item()})
+        del Ak, bk
     torch.cuda.empty_cache()
     return out
 

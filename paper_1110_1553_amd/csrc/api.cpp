@@ -225,7 +225,7 @@ int run_factor(void* dA, int64_t M, int64_t N, int64_t lda, const hqr_params& p,
   if (ex.ev_begin && (rc = record_hip(hipEventRecord((hipEvent_t)ex.ev_begin, (hipStream_t)stream),
                                       "hipEventRecord(ev_begin)")))
     return rc;
-  if ((rc = launch_persistent(p.nb, a, workers, stream, f32))) return rc;
+  if ((rc = launch_persistent(p.nb, a, workers, stream, f32, f32 && p.precision == HQR_PREC_BF16))) return rc;
   if (ex.ev_end && (rc = record_hip(hipEventRecord((hipEvent_t)ex.ev_end, (hipStream_t)stream),
                                     "hipEventRecord(ev_end)")))
     return rc;
@@ -394,7 +394,6 @@ int hqr_factor_f32(float* dA, int64_t M, int64_t N, int64_t lda, const hqr_param
   if (!params || check_params(*params)) return -5;
   hqr_params p = *params;
   if (p.precision == HQR_PREC_FP64) p.precision = HQR_PREC_FP32;
-  if (p.precision == HQR_PREC_BF16) return -5;  // BF16 products: not built
   if (!dwork) return -7;
   const Layout L = layout_for(M, N, p, 0, sizeof(float));
   if (L.mt > 65535 || L.nt > 65535) return -2;

@@ -59,6 +59,31 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 operands with FP32 accumulation (precision HQR_PREC_BF16): each
+// operand is the float rounded to the nearest bfloat16 (ties to even); the
+// product of two bfloat16 values is exact in FP32, where the matrix core
+// accumulates.  One v_mfma_f32_16x16x16_bf16 takes four consecutive values
+// of the reduction index per lane (lane l: index 4 (l / 16) + j, j < 4), the
+// same four a lane feeds into four 16x16x4 FP32 products, so it replaces a
+// group of four of them with the operands packed.
+typedef short s4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ short bf16_bits(float x) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, x);
+  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ s4 bf16x4(float a, float b, float c, float d) {
+  s4 r;
+  r.x = bf16_bits(a);
+  r.y = bf16_bits(b);
+  r.z = bf16_bits(c);
+  r.w = bf16_bits(d);
+  return r;
+}
+__device__ __forceinline__ s4 bf16x4(const f4& v) { return bf16x4(v.x, v.y, v.z, v.w); }
+__device__ __forceinline__ f4 mfma_bf(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 // Reciprocal square root and reciprocal from the hardware estimates
 // (v_rsq, v_rcp) refined by Newton steps to the working precision.  The
 // arguments are positive normal numbers (a squared column norm and the sum
@@ -322,10 +347,11 @@ __device__ __forceinline__ bool row_block_active(int rb, int p) {
 //
 // A wave may hold SPW strips (columns 16 w + 64 s, s < SPW, of the chunk):
 // every V operand read from LDS then feeds SPW products.
-template <typename E, int NB, int KIND, bool TRANS, int SPW>
+template <typename E, int NB, int KIND, bool TRANS, int SPW, bool BF = false>
 __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const E* __restrict__ Vs,
                                               const E* __restrict__ Ts, int p, E* c1, int64_t ldc,
                                               const Lane& L) {
+  static_assert(!BF || sizeof(E) == 4, "BF16 products take float tiles");
   constexpr int NRB = NB / 16;
   V4<E> c1v[SPW];
   V4<E> w0[SPW], w1[SPW];
@@ -358,15 +384,26 @@ __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const 
 #pragma unroll
           for (int r = 0; r < 4; ++r) an[r] = va[(16 * (rb + 1) + r) * LDV];
         }
+        if constexpr (BF) {
+          const s4 ab = bf16x4(a[0], a[1], a[2], a[3]);
 #pragma unroll
-        for (int s = 0; s < SPW; ++s) {
-          w0[s] = mfma(a[0], acc[s][rb][0], w0[s]);
-          w1[s] = mfma(a[1], acc[s][rb][1], w1[s]);
-        }
+          for (int s = 0; s < SPW; ++s) {
+            if (rb & 1)
+              w1[s] = mfma_bf(ab, bf16x4(acc[s][rb]), w1[s]);
+            else
+              w0[s] = mfma_bf(ab, bf16x4(acc[s][rb]), w0[s]);
+          }
+        } else {
 #pragma unroll
-        for (int s = 0; s < SPW; ++s) {
-          w0[s] = mfma(a[2], acc[s][rb][2], w0[s]);
-          w1[s] = mfma(a[3], acc[s][rb][3], w1[s]);
+          for (int s = 0; s < SPW; ++s) {
+            w0[s] = mfma(a[0], acc[s][rb][0], w0[s]);
+            w1[s] = mfma(a[1], acc[s][rb][1], w1[s]);
+          }
+#pragma unroll
+          for (int s = 0; s < SPW; ++s) {
+            w0[s] = mfma(a[2], acc[s][rb][2], w0[s]);
+            w1[s] = mfma(a[3], acc[s][rb][3], w1[s]);
+          }
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -384,8 +421,12 @@ __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const 
       V4<E> w = w0[s] + w1[s];
       if (KIND != K_UNM) w += c1v[s];
       V4<E> w2t = {E(0), E(0), E(0), E(0)};
+      if constexpr (BF) {
+        w2t = mfma_bf(bf16x4(t[0], t[1], t[2], t[3]), bf16x4(w), w2t);
+      } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) w2t = mfma(t[r], w[r], w2t);
+        for (int r = 0; r < 4; ++r) w2t = mfma(t[r], w[r], w2t);
+      }
       if (KIND != K_UNM) st4(rc1, 4 * L.g + (L.q + 64 * s) * (int)ldc, c1v[s] - w2t);
       wn[s] = -w2t;
     }
@@ -405,12 +446,23 @@ __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const 
           b0[r] = act0 ? vc[16 * rb * LDV + r] : E(0);
           b1[r] = act1 ? vc[16 * (rb + 1) * LDV + r] : E(0);
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        if constexpr (BF) {
+          const s4 bb0 = bf16x4(b0[0], b0[1], b0[2], b0[3]);
+          const s4 bb1 = bf16x4(b1[0], b1[1], b1[2], b1[3]);
 #pragma unroll
           for (int s = 0; s < SPW; ++s) {
-            if (act0) acc[s][rb] = mfma(b0[r], wn[s][r], acc[s][rb]);
-            if (act1) acc[s][rb + 1] = mfma(b1[r], wn[s][r], acc[s][rb + 1]);
+            const s4 wb = bf16x4(wn[s]);
+            if (act0) acc[s][rb] = mfma_bf(bb0, wb, acc[s][rb]);
+            if (act1) acc[s][rb + 1] = mfma_bf(bb1, wb, acc[s][rb + 1]);
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int s = 0; s < SPW; ++s) {
+              if (act0) acc[s][rb] = mfma(b0[r], wn[s][r], acc[s][rb]);
+              if (act1) acc[s][rb + 1] = mfma(b1[r], wn[s][r], acc[s][rb + 1]);
+            }
           }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -420,11 +472,11 @@ __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const 
 }
 
 // One strip per wave.
-template <typename E, int NB, int KIND, bool TRANS = true>
+template <typename E, int NB, int KIND, bool TRANS = true, bool BF = false>
 __device__ __forceinline__ void apply_panel(V4<E> (&acc)[NB / 16], const E* __restrict__ Vs,
                                             const E* __restrict__ Ts, int p, E* c1, int64_t ldc,
                                             const Lane& L) {
-  apply_panel_n<E, NB, KIND, TRANS, 1>(reinterpret_cast<V4<E> (&)[1][NB / 16]>(acc), Vs, Ts, p, c1, ldc, L);
+  apply_panel_n<E, NB, KIND, TRANS, 1, BF>(reinterpret_cast<V4<E> (&)[1][NB / 16]>(acc), Vs, Ts, p, c1, ldc, L);
 }
 
 template <typename E, int NB, int KIND>
@@ -506,7 +558,7 @@ __device__ __forceinline__ void stage_panel(const PanelPrefetch<E, NB>& pf, E* V
 // (the panels in reverse order, T).  Only the first np panels are applied:
 // the panels after them are identities (T = 0, the zero padding beyond the
 // last matrix column of a ragged tile column).
-template <typename E, int NB, int KIND, bool TRANS, int CW>
+template <typename E, int NB, int KIND, bool TRANS, int CW, bool BF = false>
 __device__ __forceinline__ void run_update(Smem<E, NB>& sm, const E* V, const E* T, E* C1, E* C2,
                                            int64_t ld, int np = NB / IB) {
   const int NP = __builtin_amdgcn_readfirstlane(np);
@@ -529,7 +581,7 @@ __device__ __forceinline__ void run_update(Smem<E, NB>& sm, const E* V, const E*
       const int pn = TRANS ? p + 1 : p - 1;
       prefetch_panel<E, NB, KIND>(pf, V, ld, T + pn * 256, pn);
     }
-    if (on) apply_panel<E, NB, KIND, TRANS>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p, ld, L);
+    if (on) apply_panel<E, NB, KIND, TRANS, BF>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p, ld, L);
   }
   if (on) store_strip<E, NB, K_TS>(acc, C2 + coloff, ld, 0, L);
 }
@@ -880,7 +932,7 @@ __device__ __forceinline__ void panel_block(E* A, E* R, E* T, int b) {
 //
 // Applies panel p (V_p, T_p staged in sm.V[0], sm.T[0]) to the strips
 // p+1 .. s_last of the tile(s) (at most 3): wave w takes strip p + 1 + w.
-template <typename E, int NB, int KIND>
+template <typename E, int NB, int KIND, bool BF = false>
 __device__ __forceinline__ void panel_strips_4w(E* A, E* R, int p, int s_last) {
   p = __builtin_amdgcn_readfirstlane(p);
   s_last = __builtin_amdgcn_readfirstlane(s_last);
@@ -891,7 +943,7 @@ __device__ __forceinline__ void panel_strips_4w(E* A, E* R, int p, int s_last) {
     V4<E> acc[NB / 16];
     E* strip = A + (int64_t)(16 * s) * NB;
     load_strip<E, NB, KIND>(acc, strip, NB, p, L);
-    apply_panel<E, NB, KIND>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p,
+    apply_panel<E, NB, KIND, true, BF>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p,
                           NB, L);
     store_strip<E, NB, KIND>(acc, strip, NB, p, L);
   }
@@ -904,7 +956,7 @@ __device__ __forceinline__ void panel_strips_4w(E* A, E* R, int p, int s_last) {
 // already factored and T from `T`, the strips held in registers across the
 // panels.  Done right before block b is factored, so that block b depends on
 // nothing that a predecessor task writes later than its own block b.
-template <typename E, int NB, int KIND>
+template <typename E, int NB, int KIND, bool BF = false>
 __device__ __forceinline__ void panel_left_update_4w(E* A, E* R, const E* T, int b) {
   constexpr int NRB = NB / 16;
   b = __builtin_amdgcn_readfirstlane(b);
@@ -930,7 +982,7 @@ __device__ __forceinline__ void panel_left_update_4w(E* A, E* R, const E* T, int
     lds_barrier();
     if (p + 1 < np) prefetch_panel<E, NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
     if (on)
-      apply_panel<E, NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
+      apply_panel<E, NB, KIND, true, BF>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : R + (int64_t)(16 * s) * NB + 16 * p, NB, L);
   }
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb)
@@ -1208,7 +1260,7 @@ __device__ __forceinline__ E* t_block(void* T, const LaunchArgs& a, int nb, int 
 // takes this task's earlier panels, is factored, and is published at once
 // (except the last active block, published by finish_task).  Returns 0 when
 // the launch was aborted while waiting.
-template <typename E, int NB, int KIND>
+template <typename E, int NB, int KIND, bool BF = false>
 __device__ __noinline__ int panel_task(const LaunchArgs& a, int t, const DevTask& task) {
   E* T = t_block<E>((KIND == K_UNM) ? a.Tg : a.Tk, a, NB, task.row, task.k);
   E* A = tile_ptr<E>(a, NB, task.row, task.k);
@@ -1228,10 +1280,10 @@ __device__ __noinline__ int panel_task(const LaunchArgs& a, int t, const DevTask
       return 0;
     }
     if constexpr (sizeof(E) == 4) {
-      if (b > 0) panel_left_update_4w<E, NB, KIND>(A, R, T, b);
+      if (b > 0) panel_left_update_4w<E, NB, KIND, BF>(A, R, T, b);
       for (int p = 4 * b; p < 4 * b + 4; ++p) {
         panel_columns<E, NB, KIND>(A, R, T, p);
-        if (p < 4 * b + 3) panel_strips_4w<E, NB, KIND>(A, R, p, 4 * b + 3);
+        if (p < 4 * b + 3) panel_strips_4w<E, NB, KIND, BF>(A, R, p, 4 * b + 3);
       }
     } else {
       panel_block<E, NB, KIND>(A, R, T, b);
@@ -1249,7 +1301,7 @@ __device__ __noinline__ int panel_task(const LaunchArgs& a, int t, const DevTask
 
 // An update task covers one or two 64-column sub-chunks (one 16-column
 // strip per wave; one sub-chunk at nb = 64 and at the ragged end of a tile).
-template <typename E, int NB, int KIND>
+template <typename E, int NB, int KIND, bool BF = false>
 __device__ __noinline__ void update_task(const LaunchArgs& a, const DevTask& task) {
   void* T = (KIND == K_UNM) ? a.Tg : a.Tk;
   const int64_t colchunk = (int64_t)task.chunk * 64 * NB;
@@ -1261,9 +1313,9 @@ __device__ __noinline__ void update_task(const LaunchArgs& a, const DevTask& tas
   // 64-column block up to its last active block (task.pad & 0xff)
   const int np = 4 * ((task.pad & 0xff) + 1) < NB / IB ? 4 * ((task.pad & 0xff) + 1) : NB / IB;
   if (NB >= 128 && (task.pad >> 8) == 2)
-    run_update<E, NB, KIND, true, 128>(smem<E, NB>(), V, Tb, C1, C2, NB, np);
+    run_update<E, NB, KIND, true, 128, BF>(smem<E, NB>(), V, Tb, C1, C2, NB, np);
   else
-    run_update<E, NB, KIND, true, 64>(smem<E, NB>(), V, Tb, C1, C2, NB, np);
+    run_update<E, NB, KIND, true, 64, BF>(smem<E, NB>(), V, Tb, C1, C2, NB, np);
 }
 
 // Block of 64 columns of B (nb x 64, column-major) of tile row r.
@@ -1303,7 +1355,7 @@ __device__ __forceinline__ void bind_problem(LaunchArgs& la, const LaunchArgs& a
 // Every task a workgroup waits for was taken earlier by a running
 // workgroup, so the wait always ends.  BATCH: the tasks of many independent
 // problems share the cursor (each task names its problem).
-template <typename E, int NB, bool BATCH>
+template <typename E, int NB, bool BATCH, bool BF = false>
 __global__ __launch_bounds__(NT, 1) void persistent_kernel(LaunchArgs args) {
   LaunchArgs la = args;
   if (threadIdx.x == 0) smem<E, NB>().next = -2;
@@ -1331,12 +1383,12 @@ __global__ __launch_bounds__(NT, 1) void persistent_kernel(LaunchArgs args) {
       }
     } else {
       switch (task.op) {
-        case GEQRT: ok = panel_task<E, NB, K_UNM>(a, t, task); break;
-        case TSQRT: ok = panel_task<E, NB, K_TS>(a, t, task); break;
-        case TTQRT: ok = panel_task<E, NB, K_TT>(a, t, task); break;
-        case UNMQR: update_task<E, NB, K_UNM>(a, task); break;
-        case TSMQR: update_task<E, NB, K_TS>(a, task); break;
-        default: update_task<E, NB, K_TT>(a, task); break;
+        case GEQRT: ok = panel_task<E, NB, K_UNM, BF>(a, t, task); break;
+        case TSQRT: ok = panel_task<E, NB, K_TS, BF>(a, t, task); break;
+        case TTQRT: ok = panel_task<E, NB, K_TT, BF>(a, t, task); break;
+        case UNMQR: update_task<E, NB, K_UNM, BF>(a, task); break;
+        case TSMQR: update_task<E, NB, K_TS, BF>(a, task); break;
+        default: update_task<E, NB, K_TT, BF>(a, task); break;
       }
     }
     if (!ok) break;  // aborted inside a panel task
@@ -1864,7 +1916,7 @@ int default_workers(int nb, bool f32) {
   }
 }
 
-template <typename E>
+template <typename E, bool BF = false>
 static int launch_persistent_t(int nb, const LaunchArgs& a, int workers, hipStream_t s) {
   const dim3 g(workers), b(NT);
   if (a.probs) {
@@ -1876,19 +1928,21 @@ static int launch_persistent_t(int nb, const LaunchArgs& a, int workers, hipStre
     }
   } else {
     switch (nb) {
-      case 64: hipLaunchKernelGGL((persistent_kernel<E, 64, false>), g, b, sizeof(Smem<E, 64>), s, a); break;
-      case 128: hipLaunchKernelGGL((persistent_kernel<E, 128, false>), g, b, sizeof(Smem<E, 128>), s, a); break;
-      case 256: hipLaunchKernelGGL((persistent_kernel<E, 256, false>), g, b, sizeof(Smem<E, 256>), s, a); break;
+      case 64: hipLaunchKernelGGL((persistent_kernel<E, 64, false, BF>), g, b, sizeof(Smem<E, 64>), s, a); break;
+      case 128: hipLaunchKernelGGL((persistent_kernel<E, 128, false, BF>), g, b, sizeof(Smem<E, 128>), s, a); break;
+      case 256: hipLaunchKernelGGL((persistent_kernel<E, 256, false, BF>), g, b, sizeof(Smem<E, 256>), s, a); break;
       default: return HQR_ERR_INTERNAL;
     }
   }
   return record_hip(hipGetLastError(), "persistent_kernel launch");
 }
 
-int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream, bool f32) {
+int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream, bool f32, bool bf16) {
   if (workers < 1) workers = 1;
-  // the batched path runs in FP64 only
+  // the batched path runs in FP64 only; BF16 products take float tiles
   if (f32 && a.probs) return HQR_ERR_INTERNAL;
+  if (bf16 && (!f32 || a.B)) return HQR_ERR_INTERNAL;
+  if (bf16) return launch_persistent_t<float, true>(nb, a, workers, (hipStream_t)stream);
   return f32 ? launch_persistent_t<float>(nb, a, workers, (hipStream_t)stream)
              : launch_persistent_t<double>(nb, a, workers, (hipStream_t)stream);
 }

@@ -84,7 +84,6 @@ int hqr_lstsq_ir(const double* dA, int64_t M, int64_t N, int64_t lda, const doub
   if (!db) return -5;
   if (!dx) return -6;
   if (!params || check_params(*params)) return -8;
-  if (params->precision == HQR_PREC_BF16) return -8;  // BF16 factors: not built
   hqr_exec ex{0, 0, 0, nullptr, nullptr};
   if (exec) ex = *exec;
   if (ex.order != 0 && ex.order != 1) return -9;

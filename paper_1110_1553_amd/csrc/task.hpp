@@ -73,8 +73,10 @@ int launch_check_sig(const int32_t* fctrl, const FactorSig& sig, int32_t* bctrl,
 // Run every task of the plan in one persistent launch of `workers`
 // workgroups.  nb is 64, 128 or 256.
 // f32: the tiles, T factors and B blocks hold float and the tile kernels
-// run in FP32 (single-problem launches only).
-int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream, bool f32 = false);
+// run in FP32 (single-problem launches only); bf16 (with f32, factorization
+// launches only): the block-reflector products take BF16 operands and
+// accumulate in FP32.
+int launch_persistent(int nb, const LaunchArgs& a, int workers, void* stream, bool f32 = false, bool bf16 = false);
 
 // Copies the column-major M x N matrix A (leading dimension lda) into the
 // blocked buffer At (mt x nt blocks of nb rows x tw columns, zero padding
