@@ -41,8 +41,10 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # copy-in kernel of known size.  Valid only for the kernel source they were
 # measured on (first 16 hex digits of the SHA-256 of csrc/kernels.hip).
 TRAFFIC = {
-    "tall-hqr": {"kernels_sha256": "946688304872c621", "read": 41.09e9, "write": 39.98e9,
+    "tall-hqr": {"kernels_sha256": "2bc79495b446c5cc", "read": 39.99e9, "write": 39.62e9,
                  "profile": "profiles/persistent_kernel_tall-hqr.md"},
+    "square-flat": {"kernels_sha256": "2bc79495b446c5cc", "read": 177.61e9, "write": 185.54e9,
+                    "profile": "profiles/persistent_kernel_square-flat.md"},
 }
 
 
