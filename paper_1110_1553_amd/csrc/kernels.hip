@@ -626,9 +626,11 @@ __device__ __forceinline__ double readlane(double v, int lane) {
 // kind), T_p in sm.T[0] and in `T`, and the factored columns in A (and R).
 // XL: the panel's columns are taken from sm.V[0] (row-major, stride LDV,
 // left there by panel_block) instead of from memory.
-template <typename E, int NB, int KIND, bool XL = false>
-__device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
-  constexpr int NM = NB / 16;  // row slots per thread
+template <typename E, int NB, int KIND, bool XL, int NS>
+__device__ __forceinline__ void panel_columns_ns(E* A, E* R, E* T, int p) {
+  // NS row slots per thread are held (NB / 16 for TS; for GEQRT and TT the
+  // slots that can hold rows of this panel, rounded up to a multiple of 4)
+  constexpr int NM = NS;
   p = __builtin_amdgcn_readfirstlane(p);  // uniform: row-slot guards become scalar branches
   Smem<E, NB>& sm = smem<E, NB>();
   const int tid = threadIdx.x;
@@ -641,7 +643,7 @@ __device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
   // row slots that can hold rows of the panel (uniform): GEQRT rows < NB,
   // TT rows <= c0 + 15.  The other slots hold zeros; the column loop runs
   // over all slots (branch-free), only loads and stores skip them.
-  const int nm = (KIND == K_UNM) ? NM - p : (KIND == K_TT ? p + 1 : NM);
+  const int nm = (KIND == K_UNM) ? NB / 16 - p : (KIND == K_TT ? p + 1 : NB / 16);
   E* Vs = sm.V[0];
   E* Ts = sm.T[0];
   E* Zs = sm.R;     // Gram entries v_i^T v_j of the panel
@@ -799,6 +801,32 @@ __device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
   // V_p and T_p in LDS are what the strips of the block need next; the
   // columns just stored are read back (block update) only after a full barrier
   lds_barrier();
+}
+
+// The column loop's cost follows the rows a panel can hold: GEQRT panel p
+// has rows 16p .. NB-1 (NB/16 - p slots), TTQRT panel p rows 0 .. 16p+15
+// (p + 1 slots); TSQRT always all NB/16.  The slot count is rounded up to a
+// multiple of 4 so that each kind has at most four instantiations.
+template <typename E, int NB, int KIND, bool XL = false>
+__device__ __forceinline__ void panel_columns(E* A, E* R, E* T, int p) {
+  constexpr int NM = NB / 16;
+  p = __builtin_amdgcn_readfirstlane(p);
+  if constexpr (KIND == K_TS || NM <= 4) {
+    panel_columns_ns<E, NB, KIND, XL, NM>(A, R, T, p);
+  } else {
+    const int nm = (KIND == K_UNM) ? NM - p : p + 1;
+    const int g = (nm + 3) >> 2;  // uniform
+    if (g == 1) {
+      panel_columns_ns<E, NB, KIND, XL, 4>(A, R, T, p);
+    } else if (g == 2) {
+      panel_columns_ns<E, NB, KIND, XL, 8>(A, R, T, p);
+    } else if constexpr (NM > 8) {
+      if (g == 3)
+        panel_columns_ns<E, NB, KIND, XL, 12>(A, R, T, p);
+      else
+        panel_columns_ns<E, NB, KIND, XL, NM>(A, R, T, p);
+    }
+  }
 }
 
 // Row-split application of panel p inside a panel task: the strip of 16
