@@ -371,7 +371,10 @@ int hqr_lstsq_noalloc(double* dA, int64_t M, int64_t N, int64_t lda, double* dB,
  *
  * min ||A x - b|| for a double A (M x N, M >= N, full rank) and one
  * right-hand side: A is rounded to float and factored by the FP32 tiled QR
- * (as hqr_factor_f32); then the augmented system [I A; A^T 0][r; x] = [b; 0]
+ * (as hqr_factor_f32, with b carried along as a further tile column so that
+ * the factorization also forms Q^T b); the first iterate is the FP32
+ * solution x = R^{-1} (Q^T b)(0:N) with r = b - A x in FP64; then the
+ * augmented system [I A; A^T 0][r; x] = [b; 0]
  * is refined (Bjorck's iterative refinement for least squares): each
  * iteration forms f = b - r - A x and g = -A^T r in FP64 from the original
  * double A, solves the correction with the FP32 factors (Q applied in FP32,
@@ -379,10 +382,13 @@ int hqr_lstsq_noalloc(double* dA, int64_t M, int64_t N, int64_t lda, double* dB,
  * in FP64.  It converges when the condition number of A times the float
  * unit roundoff (6e-8) is well below 1. */
 typedef struct hqr_ir_info {
-  int32_t iterations;  /* corrections applied (the first one gives the FP32 solution) */
+  int32_t iterations;  /* corrections applied, the FP32 solution counted as the first */
   int32_t converged;   /* 1 when eta <= tol */
   double eta;          /* backward error of the returned (x, r), see hqr_lstsq_ir */
-  double history[32];  /* eta before each of the first 32 corrections (history[0] = 1: x = r = 0) */
+  double history[32];  /* eta before each of the first 32 corrections (history[0] = 1: x = r = 0;
+                          history[1] = eta of the FP32 solution) */
+  int32_t history_len; /* entries of history written (a last one larger than the one before it is the
+                          eta of a rejected correction) */
 } hqr_ir_info;
 
 /* Workspace bytes of hqr_lstsq_ir (FP32 factorization, one FP32 block

@@ -235,7 +235,7 @@ def lstsq_ir(A, b, params, exec_=None, max_iter=30, tol=1e-12, stream=None, resi
     info = _lib.lstsq_ir_ptr(A.data_ptr(), M, N, lda, b.data_ptr(), x.data_ptr(), r.data_ptr() if residual else 0,
                              params, exec_, max_iter, tol, work.data_ptr(), nbytes, s.cuda_stream)
     out = {"iterations": info.iterations, "converged": bool(info.converged), "eta": info.eta,
-           "history": list(info.history[: min(info.iterations, 32)])}
+           "history": list(info.history[: info.history_len])}
     return (x, r, out) if residual else (x, out)
 
 

@@ -44,7 +44,7 @@ class DagInfo(ctypes.Structure):
 
 class IrInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("eta", ctypes.c_double),
-                ("history", ctypes.c_double * 32)]
+                ("history", ctypes.c_double * 32), ("history_len", ctypes.c_int32)]
 
 
 TASK_DTYPE = np.dtype([("op", "u1"), ("chunk", "u1"), ("row", "<u2"), ("killer", "<u2"), ("k", "<u2"),

@@ -9,8 +9,11 @@
 // With A = Q [R; 0], the correction of the residuals f = b - r - A x and
 // g = -A^T r is
 //     h = R^{-T} g,   d = Q^T f,   dx = R^{-1} (d(0:N) - h),   dr = Q [h; d(N:M)]
-// and x += dx, r += dr.  Starting from x = 0, r = 0 the first correction is
-// the plain FP32 least-squares solution.  The iterate is judged by the
+// and x += dx, r += dr.  The first iterate is the FP32 least-squares
+// solution x = R^{-1} (Q^T b)(0:N), with Q^T b left in a tile column that
+// the factorization carries along, and r = b - A x in FP64: the first
+// correction from x = r = 0 gives the same x at the cost of two Q
+// applications (and an FP32 r).  The iterate is judged by the
 // normwise backward error of the augmented system,
 //     eta = sqrt(||f||^2 + ||g||^2) / (||A||_F (||x|| + ||r||) + ||b||),
 // evaluated before each correction; the loop stops once eta <= tol, when a
@@ -18,7 +21,8 @@
 // iterate before that correction is returned), or after max_iter
 // corrections.
 //
-// Workspace: the FP32 factorization (tiles and T factors), the FP32 block of
+// Workspace: the FP32 factorization (tiles and T factors, b as a further
+// tile column), the FP32 block of
 // the Q applications, then the FP64 vectors x (N), r (M), f (M), g (N),
 // y (N) and four words for the norms.
 #include <hip/hip_runtime.h>
@@ -42,7 +46,7 @@ struct IrLayout {
 
 IrLayout ir_layout(int64_t M, int64_t N, const hqr_params& p) {
   IrLayout L{};
-  L.fac = layout_for(M, N, p, 0, sizeof(float));
+  L.fac = layout_for(M, N, p, 1, sizeof(float));  // b carried as a tile column
   L.app = apply_layout_for(M, 1, p, sizeof(float));
   size_t off = L.fac.total;
   L.app_off = off; off = align256(off + L.app.total);
@@ -109,11 +113,25 @@ int hqr_lstsq_ir(const double* dA, int64_t M, int64_t N, int64_t lda, const doub
   void* bwork = w + L.app_off;
   hipStream_t s = (hipStream_t)stream;
   int rc;
-  // FP32 factorization of A (A itself is left untouched: copied and rounded into the tiles)
-  if ((rc = run_factor(const_cast<double*>(dA), M, N, lda, p, ex, dwork, nullptr, 0, 0, stream, false, true, false)))
+  // FP32 factorization of A with b carried along as a tile column, so that
+  // the update kernels leave Q^T b in it (A and b themselves are left
+  // untouched: copied and rounded into the tiles)
+  if ((rc = run_factor(const_cast<double*>(dA), M, N, lda, p, ex, dwork, const_cast<double*>(db), M, 1, stream, false,
+                       true, false)))
     return rc;
-  // x = 0, r = 0
-  if ((rc = launch_zero_i32((int32_t*)x, (int64_t)((L.f - L.x) / sizeof(int32_t)), stream))) return rc;
+  // the FP32 least-squares solution x = R^{-1} (Q^T b)(0:N), and its
+  // residual r = b - A x in FP64: the first correction of the iteration from
+  // x = r = 0, without its two Q applications
+  {
+    const float* Bt = Rt + (size_t)L.fac.mt * L.fac.nt * p.nb * p.nb;
+    if ((rc = launch_tile_copy(f, 0, M, const_cast<float*>(Bt), 1, M, 1, p.nb, p.nb, L.fac.mt, 1, false, stream)))
+      return rc;
+    if ((rc = record_hip(hipMemcpyAsync(x, f, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s),
+                         "hipMemcpyAsync(x0)")))
+      return rc;
+    if ((rc = launch_ir_trsv(Rt, p.nb, L.fac.mt, N, x, false, stream))) return rc;
+    if ((rc = launch_ir_residual(dA, lda, M, N, x, db, nullptr, r, stream))) return rc;
+  }
   // ||A||_F and ||b||, once
   auto read_norms = [&](double* host) -> int {
     if (int e = record_hip(hipMemcpyAsync(host, norms, 4 * sizeof(double), hipMemcpyDeviceToHost, s),
@@ -130,7 +148,11 @@ int hqr_lstsq_ir(const double* dA, int64_t M, int64_t N, int64_t lda, const doub
   double nrm[4];
   if ((rc = read_norms(nrm))) return rc;
   const double normA = std::sqrt(nrm[0]), normb = std::sqrt(nrm[1]);
-  int it = 0;
+  int it = 1;  // the FP32 solution counts as the first correction
+  if (info) {
+    info->history[0] = 1.0;  // x = r = 0
+    info->history_len = 1;
+  }
   double eta = INFINITY, prev = INFINITY;
   bool converged = false;
   for (;;) {
@@ -144,7 +166,10 @@ int hqr_lstsq_ir(const double* dA, int64_t M, int64_t N, int64_t lda, const doub
     if ((rc = read_norms(nrm))) return rc;
     const double den = normA * (std::sqrt(nrm[2]) + std::sqrt(nrm[3])) + normb;
     eta = den > 0.0 ? std::sqrt(nrm[0] + nrm[1]) / den : 0.0;
-    if (info && it < 32) info->history[it] = eta;
+    if (info && it < 32) {
+      info->history[it] = eta;
+      info->history_len = it + 1;
+    }
     if (eta <= tol) {
       converged = true;
       break;
