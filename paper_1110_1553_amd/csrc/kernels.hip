@@ -222,25 +222,8 @@ template <>
 __device__ __forceinline__ float bload1<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-template <typename E>
-__device__ __forceinline__ V4<E> ld4(__amdgpu_buffer_rsrc_t r, int off);
-template <>
-__device__ __forceinline__ d4 ld4<double>(__amdgpu_buffer_rsrc_t r, int off) {
-  const d2 x = bload2<double>(r, off);
-  const d2 y = bload2<double>(r, off + 2);
-  d4 v;
-  v.x = x.x; v.y = x.y; v.z = y.x; v.w = y.y;
-  return v;
-}
-template <>
-__device__ __forceinline__ f4 ld4<float>(__amdgpu_buffer_rsrc_t r, int off) {
+__device__ __forceinline__ f4 ld4(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off * 4, 0, kCoherent));
-}
-__device__ __forceinline__ void st4(__amdgpu_buffer_rsrc_t r, int off, d4 v) {
-  d2 x, y;
-  x.x = v.x; x.y = v.y; y.x = v.z; y.y = v.w;
-  bstore2(r, off, x);
-  bstore2(r, off + 2, y);
 }
 __device__ __forceinline__ void st4(__amdgpu_buffer_rsrc_t r, int off, f4 v) {
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off * 4, 0, kCoherent);
@@ -283,14 +266,20 @@ __device__ __forceinline__ void lds_barrier() {
 
 template <typename E, int NB>
 struct Smem {
-  E V[2][NB * LDV];  // staged V panels (row-major, stride LDV)
-  E T[2][IB * LDV];  // staged T blocks
+  // staged V panels (row-major, stride LDV) and T blocks: the update tasks
+  // stage two panels at a time into slots {0, 1} and {2, 3} alternately;
+  // the panel tasks use slots 0 and 1 only
+  E V[4][NB * LDV];
+  E T[4][IB * LDV];
   E R[IB * LDV];     // diagonal block of the killer's R (TS/TT panel kernels)
   E tau[IB];
-  V4<E> xw[8 * 64];  // partial W = V^T C of each wave (row-split panel updates)
   int task;  // index of the task taken by the workgroup (-1: launch aborted)
   int next;  // the following task index, taken ahead by finish_task (-2: none)
   int ok;    // 1 if the task's dependencies were met, 0 if the launch was aborted
+  // partial W = V^T C of each wave (row-split updates of the panel tasks),
+  // kept in V slots 2 and 3, which only the update tasks use
+  static_assert(2 * NB * LDV * sizeof(E) >= 8 * 64 * sizeof(V4<E>), "xw does not fit in V slots 2-3");
+  __device__ V4<E>* xw() { return reinterpret_cast<V4<E>*>(V[2]); }
 };
 
 // The scheduler's shared state and the tile kernels' staging buffers live in
@@ -310,16 +299,62 @@ struct Lane {
     wave = __builtin_amdgcn_readfirstlane(t >> 6);
     g = (t >> 4) & 3;
     q = t & 15;
-    pq = 4 * (q & 3) + (q >> 2);
+    pq = 2 * (q & 3) + ((q >> 2) & 1) + 8 * (q >> 3);
   }
 };
 
+// Rows of a 16 x 16 block held in an MFMA accumulator.  Element r of lane
+// (g, q) (g = lane / 16, q = lane % 16) holds column q and the matrix row
+//     FP64: 2g + (r & 1) + 8 (r >> 1)   (rows 2g, 2g+1, 2g+8, 2g+9)
+//     FP32: 4g + r
+// FP32 accumulators hold MFMA row 4g + r, so its map is the identity.  The
+// FP64 accumulator holds MFMA row g + 4r (measured on gfx950); matrix row x
+// then sits at MFMA row pi^-1(x) with pi(g + 4r) = 2g + (r & 1) + 8 (r >> 1).
+// Either way the four lanes of a column cover its 16 rows as two contiguous
+// 64-byte halves (FP64: two 16-byte accesses per lane) or one 64-byte run
+// (FP32), so each access instruction writes whole segments: with four
+// consecutive FP64 rows per lane the lanes of a column interleave at a
+// 32-byte stride, which took twice as long to store.
+template <typename E>
+__device__ __forceinline__ int arow(const Lane& L) {  // row of element 0
+  return sizeof(E) == 8 ? 2 * L.g : 4 * L.g;
+}
+template <typename E>
+__device__ __forceinline__ int roff(int r) {  // row of element r minus that of element 0
+  return sizeof(E) == 8 ? (r & 1) + 8 * (r >> 1) : r;
+}
+
 // MFMA row whose reduction index this lane supplies in the products with
-// V^T and T^T: pi(q) for FP64 (its accumulator rows are interleaved),
-// q itself for FP32 (element r of lane l is MFMA row 4 (l / 16) + r).
+// V^T and T^T: pi(q) for FP64, q itself for FP32.
 template <typename E>
 __device__ __forceinline__ int mrow(const Lane& L) {
   return sizeof(E) == 8 ? L.pq : L.q;
+}
+
+// One column's four rows of a 16-row block in accumulator order: `off` is
+// the element offset of the block's row 0 in that column.
+template <typename E>
+__device__ __forceinline__ V4<E> ldblk(__amdgpu_buffer_rsrc_t r, int off, const Lane& L);
+template <>
+__device__ __forceinline__ d4 ldblk<double>(__amdgpu_buffer_rsrc_t r, int off, const Lane& L) {
+  const d2 x = bload2<double>(r, off + 2 * L.g);
+  const d2 y = bload2<double>(r, off + 2 * L.g + 8);
+  d4 v;
+  v.x = x.x; v.y = x.y; v.z = y.x; v.w = y.y;
+  return v;
+}
+template <>
+__device__ __forceinline__ f4 ldblk<float>(__amdgpu_buffer_rsrc_t r, int off, const Lane& L) {
+  return ld4(r, off + 4 * L.g);
+}
+__device__ __forceinline__ void stblk(__amdgpu_buffer_rsrc_t r, int off, const Lane& L, d4 v) {
+  d2 x, y;
+  x.x = v.x; x.y = v.y; y.x = v.z; y.y = v.w;
+  bstore2(r, off + 2 * L.g, x);
+  bstore2(r, off + 2 * L.g + 8, y);
+}
+__device__ __forceinline__ void stblk(__amdgpu_buffer_rsrc_t r, int off, const Lane& L, f4 v) {
+  st4(r, off + 4 * L.g, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -359,13 +394,13 @@ __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const 
 #pragma unroll
   for (int s = 0; s < SPW; ++s) {
     c1v[s] = V4<E>{E(0), E(0), E(0), E(0)};
-    if (KIND != K_UNM) c1v[s] = ld4<E>(rc1, 4 * L.g + (L.q + 64 * s) * (int)ldc);
+    if (KIND != K_UNM) c1v[s] = ldblk<E>(rc1, (L.q + 64 * s) * (int)ldc, L);
     w0[s] = V4<E>{E(0), E(0), E(0), E(0)};
     w1[s] = w0[s];
   }
   // ---- W = V^T acc: group rb = 4 products per strip, alternating two partial sums
   {
-    const E* va = Vs + 4 * L.g * LDV + mrow<E>(L);  // + (16 rb + r) * LDV
+    const E* va = Vs + arow<E>(L) * LDV + mrow<E>(L);  // + (16 rb + roff(r)) * LDV
     E a[4], an[4];
     const int lo = (KIND == K_UNM) ? p : 0;
 #pragma unroll
@@ -374,7 +409,7 @@ __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const 
     for (int rb = 0; rb < NRB; ++rb)
       if (rb == lo) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = va[(16 * rb + r) * LDV];
+        for (int r = 0; r < 4; ++r) a[r] = va[(16 * rb + roff<E>(r)) * LDV];
       }
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) {
@@ -382,7 +417,7 @@ __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const 
         __builtin_amdgcn_sched_barrier(0);
         if (rb + 1 < NRB && row_block_active<E, NB, KIND>(rb + 1, p)) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) an[r] = va[(16 * (rb + 1) + r) * LDV];
+          for (int r = 0; r < 4; ++r) an[r] = va[(16 * (rb + 1) + roff<E>(r)) * LDV];
         }
         if constexpr (BF) {
           const s4 ab = bf16x4(a[0], a[1], a[2], a[3]);
@@ -415,7 +450,8 @@ __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const 
   {
     E t[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) t[r] = TRANS ? Ts[(4 * L.g + r) * LDV + mrow<E>(L)] : Ts[mrow<E>(L) * LDV + 4 * L.g + r];
+    for (int r = 0; r < 4; ++r)
+      t[r] = TRANS ? Ts[(arow<E>(L) + roff<E>(r)) * LDV + mrow<E>(L)] : Ts[mrow<E>(L) * LDV + arow<E>(L) + roff<E>(r)];
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
       V4<E> w = w0[s] + w1[s];
@@ -424,16 +460,23 @@ __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const 
       if constexpr (BF) {
         w2t = mfma_bf(bf16x4(t[0], t[1], t[2], t[3]), bf16x4(w), w2t);
       } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) w2t = mfma(t[r], w[r], w2t);
+        // two chains of two products: the T product sits between the two
+        // halves of the panel's work, where the two waves of a SIMD arrive
+        // together
+        V4<E> x1 = {E(0), E(0), E(0), E(0)};
+        w2t = mfma(t[0], w[0], w2t);
+        x1 = mfma(t[1], w[1], x1);
+        w2t = mfma(t[2], w[2], w2t);
+        x1 = mfma(t[3], w[3], x1);
+        w2t += x1;
       }
-      if (KIND != K_UNM) st4(rc1, 4 * L.g + (L.q + 64 * s) * (int)ldc, c1v[s] - w2t);
+      if (KIND != K_UNM) stblk(rc1, (L.q + 64 * s) * (int)ldc, L, c1v[s] - w2t);
       wn[s] = -w2t;
     }
   }
   // ---- acc -= V W: groups of two row blocks, products interleaved
   {
-    const E* vc = Vs + mrow<E>(L) * LDV + 4 * L.g;  // + 16 rb LDV + r
+    const E* vc = Vs + mrow<E>(L) * LDV + arow<E>(L);  // + 16 rb LDV + roff(r)
 #pragma unroll
     for (int rb = 0; rb < NRB; rb += 2) {
       const bool act0 = row_block_active<E, NB, KIND>(rb, p);
@@ -443,8 +486,8 @@ __device__ __forceinline__ void apply_panel_n(V4<E> (&acc)[SPW][NB / 16], const 
         E b0[4], b1[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          b0[r] = act0 ? vc[16 * rb * LDV + r] : E(0);
-          b1[r] = act1 ? vc[16 * (rb + 1) * LDV + r] : E(0);
+          b0[r] = act0 ? vc[16 * rb * LDV + roff<E>(r)] : E(0);
+          b1[r] = act1 ? vc[16 * (rb + 1) * LDV + roff<E>(r)] : E(0);
         }
         if constexpr (BF) {
           const s4 bb0 = bf16x4(b0[0], b0[1], b0[2], b0[3]);
@@ -485,7 +528,7 @@ __device__ __forceinline__ void load_strip(V4<E> (&acc)[NB / 16], const E* base,
 #pragma unroll
   for (int rb = 0; rb < NB / 16; ++rb) {
     const bool active = (KIND == K_UNM) ? (rb >= p) : (KIND == K_TT ? rb <= p : true);
-    if (active) acc[rb] = ld4<E>(rsrc(base), 16 * rb + 4 * L.g + L.q * (int)ld);
+    if (active) acc[rb] = ldblk<E>(rsrc(base), 16 * rb + L.q * (int)ld, L);
   }
 }
 
@@ -495,7 +538,7 @@ __device__ __forceinline__ void store_strip(const V4<E> (&acc)[NB / 16], E* base
 #pragma unroll
   for (int rb = 0; rb < NB / 16; ++rb) {
     const bool active = (KIND == K_UNM) ? (rb >= p) : (KIND == K_TT ? rb <= p : true);
-    if (active) st4(rsrc(base), 16 * rb + 4 * L.g + L.q * (int)ld, acc[rb]);
+    if (active) stblk(rsrc(base), 16 * rb + L.q * (int)ld, L, acc[rb]);
   }
 }
 
@@ -567,21 +610,38 @@ __device__ __forceinline__ void run_update(Smem<E, NB>& sm, const E* V, const E*
   V4<E> acc[NB / 16];
   const int64_t coloff = (int64_t)(16 * L.wave) * ld;
   if (on) load_strip<E, NB, K_TS>(acc, C2 + coloff, ld, 0, L);
+  // Panels are staged two at a time, with one barrier per pair: panel it + 2
+  // is prefetched into registers before panel it is applied and written to
+  // the other pair of slots right after (those slots were last read by the
+  // pair before, which every wave finished before the last barrier).
   PanelPrefetch<E, NB> pf;
-  const int pfirst = TRANS ? 0 : NP - 1;
-  prefetch_panel<E, NB, KIND>(pf, V, ld, T + pfirst * 256, pfirst);
+  auto pan = [&](int it) { return TRANS ? it : NP - 1 - it; };
+  auto prefetch = [&](int it) { prefetch_panel<E, NB, KIND>(pf, V, ld, T + pan(it) * 256, pan(it)); };
+  auto apply = [&](int it, int slot) {
+    const int p = pan(it);
+    if (on)
+      apply_panel<E, NB, KIND, TRANS, BF>(acc, sm.V[slot], sm.T[slot], p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p,
+                                          ld, L);
+  };
+  prefetch(0);
+  stage_panel<E, NB, KIND>(pf, sm.V[0], sm.T[0], pan(0));
+  if (NP > 1) {
+    prefetch(1);
+    stage_panel<E, NB, KIND>(pf, sm.V[1], sm.T[1], pan(1));
+  }
+  lds_barrier();
 #pragma unroll 1
-  for (int it = 0; it < NP; ++it) {
-    const int p = TRANS ? it : NP - 1 - it;
-    E* Vs = sm.V[it & 1];
-    E* Ts = sm.T[it & 1];
-    stage_panel<E, NB, KIND>(pf, Vs, Ts, p);
-    lds_barrier();
+  for (int it = 0; it < NP; it += 2) {
+    const int sl = it & 2, sn = sl ^ 2;  // slots of this pair and of the next
+    if (it + 2 < NP) prefetch(it + 2);
+    apply(it, sl);
+    if (it + 2 < NP) stage_panel<E, NB, KIND>(pf, sm.V[sn], sm.T[sn], pan(it + 2));
     if (it + 1 < NP) {
-      const int pn = TRANS ? p + 1 : p - 1;
-      prefetch_panel<E, NB, KIND>(pf, V, ld, T + pn * 256, pn);
+      if (it + 3 < NP) prefetch(it + 3);
+      apply(it + 1, sl + 1);
+      if (it + 3 < NP) stage_panel<E, NB, KIND>(pf, sm.V[sn + 1], sm.T[sn + 1], pan(it + 3));
     }
-    if (on) apply_panel<E, NB, KIND, TRANS, BF>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : C1 + coloff + 16 * p, ld, L);
+    lds_barrier();
   }
   if (on) store_strip<E, NB, K_TS>(acc, C2 + coloff, ld, 0, L);
 }
@@ -846,15 +906,15 @@ __device__ __forceinline__ void apply_panel_half(V4<E> (&acc)[NB / 32], const E*
   const int lane = threadIdx.x & 63;
   V4<E> w0 = {E(0), E(0), E(0), E(0)}, w1 = w0, c1v = w0;
   if (on) {
-    if (KIND != K_UNM) c1v = ld4<E>(rsrc(c1), 4 * L.g + L.q * (int)ldc);
-    const E* va = Vs + 4 * L.g * LDV + mrow<E>(L);
+    if (KIND != K_UNM) c1v = ldblk<E>(rsrc(c1), L.q * (int)ldc, L);
+    const E* va = Vs + arow<E>(L) * LDV + mrow<E>(L);
 #pragma unroll
     for (int i = 0; i < HRB; ++i) {
       const int rb = h * HRB + i;
       if (row_block_active<E, NB, KIND>(rb, p)) {
         E a[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = va[(16 * rb + r) * LDV];
+        for (int r = 0; r < 4; ++r) a[r] = va[(16 * rb + roff<E>(r)) * LDV];
         w0 = mfma(a[0], acc[i][0], w0);
         w1 = mfma(a[1], acc[i][1], w1);
         w0 = mfma(a[2], acc[i][2], w0);
@@ -870,20 +930,20 @@ __device__ __forceinline__ void apply_panel_half(V4<E> (&acc)[NB / 32], const E*
     if (KIND != K_UNM) w += c1v;
     E t[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) t[r] = Ts[(4 * L.g + r) * LDV + mrow<E>(L)];
+    for (int r = 0; r < 4; ++r) t[r] = Ts[(arow<E>(L) + roff<E>(r)) * LDV + mrow<E>(L)];
     V4<E> w2t = {E(0), E(0), E(0), E(0)};
 #pragma unroll
     for (int r = 0; r < 4; ++r) w2t = mfma(t[r], w[r], w2t);
-    if (KIND != K_UNM && h == 0) st4(rsrc(c1), 4 * L.g + L.q * (int)ldc, c1v - w2t);
+    if (KIND != K_UNM && h == 0) stblk(rsrc(c1), L.q * (int)ldc, L, c1v - w2t);
     const V4<E> wn = -w2t;
-    const E* vc = Vs + mrow<E>(L) * LDV + 4 * L.g;
+    const E* vc = Vs + mrow<E>(L) * LDV + arow<E>(L);
 #pragma unroll
     for (int i = 0; i < HRB; ++i) {
       const int rb = h * HRB + i;
       if (row_block_active<E, NB, KIND>(rb, p)) {
         E b0[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) b0[r] = vc[16 * rb * LDV + r];
+        for (int r = 0; r < 4; ++r) b0[r] = vc[16 * rb * LDV + roff<E>(r)];
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[i] = mfma(b0[r], wn[r], acc[i]);
       }
@@ -918,7 +978,7 @@ __device__ __forceinline__ void panel_block(E* A, E* R, E* T, int b) {
   V4<E> acc[HRB];
 #pragma unroll
   for (int i = 0; i < HRB; ++i)
-    if (h * HRB + i <= hi) acc[i] = ld4<E>(rsrc(strip), 16 * (h * HRB + i) + 4 * L.g + L.q * NB);
+    if (h * HRB + i <= hi) acc[i] = ldblk<E>(rsrc(strip), 16 * (h * HRB + i) + L.q * NB, L);
   if (np > 0) {
     PanelPrefetch<E, NB> pf;
     prefetch_panel<E, NB, KIND>(pf, A, NB, T, 0);
@@ -928,7 +988,7 @@ __device__ __forceinline__ void panel_block(E* A, E* R, E* T, int b) {
       stage_panel<E, NB, KIND>(pf, Vs, Ts, p);
       lds_barrier();
       if (p + 1 < np) prefetch_panel<E, NB, KIND>(pf, A, NB, T + (p + 1) * 256, p + 1);
-      apply_panel_half<E, NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : c1s + 16 * p, NB, L, h, true, sm.xw);
+      apply_panel_half<E, NB, KIND>(acc, Vs, Ts, p, KIND == K_UNM ? nullptr : c1s + 16 * p, NB, L, h, true, sm.xw());
     }
   }
   for (int p = 4 * b; p < 4 * b + 4; ++p) {
@@ -940,9 +1000,9 @@ __device__ __forceinline__ void panel_block(E* A, E* R, E* T, int b) {
         const int rb = h * HRB + i;
         if (rb <= hi) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) H[(16 * rb + 4 * L.g + r) * LDV + L.q] = acc[i][r];
+          for (int r = 0; r < 4; ++r) H[(16 * rb + arow<E>(L) + roff<E>(r)) * LDV + L.q] = acc[i][r];
           // GEQRT: rows above the diagonal block are final R entries
-          if (KIND == K_UNM && rb < p) st4(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB, acc[i]);
+          if (KIND == K_UNM && rb < p) stblk(rsrc(strip), 16 * rb + L.q * NB, L, acc[i]);
         }
       }
     }
@@ -950,7 +1010,7 @@ __device__ __forceinline__ void panel_block(E* A, E* R, E* T, int b) {
     panel_columns<E, NB, KIND, true>(A, R, T, p);
     if (p < 4 * b + 3)
       apply_panel_half<E, NB, KIND>(acc, sm.V[0], sm.T[0], p, KIND == K_UNM ? nullptr : c1s + 16 * p, NB, L, h, s > p,
-                                    sm.xw);
+                                    sm.xw());
   }
 }
 
@@ -1000,7 +1060,7 @@ __device__ __forceinline__ void panel_left_update_4w(E* A, E* R, const E* T, int
   V4<E> acc[NRB];
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb)
-    if (on && rb <= hi) acc[rb] = ld4<E>(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB);
+    if (on && rb <= hi) acc[rb] = ldblk<E>(rsrc(strip), 16 * rb + L.q * NB, L);
   PanelPrefetch<E, NB> pf;
   prefetch_panel<E, NB, KIND>(pf, A, NB, T, 0);
   for (int p = 0; p < np; ++p) {
@@ -1014,7 +1074,7 @@ __device__ __forceinline__ void panel_left_update_4w(E* A, E* R, const E* T, int
   }
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb)
-    if (on && rb <= hi) st4(rsrc(strip), 16 * rb + 4 * L.g + L.q * NB, acc[rb]);
+    if (on && rb <= hi) stblk(rsrc(strip), 16 * rb + L.q * NB, L, acc[rb]);
   stores_done();
   __syncthreads();  // the column loop of block b reads these strips from memory
 }

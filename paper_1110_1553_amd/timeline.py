@@ -20,7 +20,11 @@ Algorithmic work per task (nb = b):
 Usage::
 
     python -m paper_1110_1553_amd.timeline --M 131072 --N 2048 --nb 256 \\
-        --p 8 --a 4 --low greedy --high fibonacci --domino 1 [--graded] [--json out.json]
+        --p 8 --a 4 --low greedy --high fibonacci --domino 1 [--graded] [--json out.json] \\
+        [--raw out.npz]
+
+``--raw`` also saves the per-task stamps (``tl``: picked, ready, done,
+workgroup | XCD << 16) next to the plan's fields, in dispatch order.
 """
 import argparse
 import json
@@ -113,6 +117,7 @@ def main():
     ap.add_argument("--graded", action="store_true", help="U diag(sigma) V^T (square only) instead of N(0,1)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--raw", default=None, help="save the per-task stamps and the plan (numpy .npz)")
     args = ap.parse_args()
     os.environ["HQR_TIMELINE"] = "1"  # read by the library at its first launch
     import torch
@@ -150,6 +155,10 @@ def main():
     if args.json:
         with open(args.json, "w") as f:
             json.dump(s, f, indent=1)
+    if args.raw:
+        import numpy as np
+
+        np.savez_compressed(args.raw, tl=tl, **{f: tasks[f] for f in tasks.dtype.names})
     sys.stdout.flush()
 
 
