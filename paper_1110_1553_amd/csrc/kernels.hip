@@ -609,7 +609,6 @@ __device__ __forceinline__ void run_update(Smem<E, NB>& sm, const E* V, const E*
   const bool on = 16 * L.wave < CW;  // waves holding a strip of the chunk (uniform per wave)
   V4<E> acc[NB / 16];
   const int64_t coloff = (int64_t)(16 * L.wave) * ld;
-  if (on) load_strip<E, NB, K_TS>(acc, C2 + coloff, ld, 0, L);
   // Panels are staged two at a time, with one barrier per pair: panel it + 2
   // is prefetched into registers before panel it is applied and written to
   // the other pair of slots right after (those slots were last read by the
@@ -629,6 +628,9 @@ __device__ __forceinline__ void run_update(Smem<E, NB>& sm, const E* V, const E*
     prefetch(1);
     stage_panel<E, NB, KIND>(pf, sm.V[1], sm.T[1], pan(1));
   }
+  // the chunk is loaded last: the first panel's products take its row
+  // blocks in order as they arrive
+  if (on) load_strip<E, NB, K_TS>(acc, C2 + coloff, ld, 0, L);
   lds_barrier();
 #pragma unroll 1
   for (int it = 0; it < NP; it += 2) {
