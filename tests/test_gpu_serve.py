@@ -19,24 +19,31 @@ def say(msg):
     sys.stdout.flush()
 
 
-def test_served_results_equal_lone_solves(cuda):
+# nb = 64 with a Greedy tree, and the tile size and tree the serving
+# benchmark's autotuner picks (nb = 256, TS domains of 4 under Greedy)
+SERVE_CASES = [dict(tree=dict(nb=64, low="greedy"), mhi=2000, nhi=160, budget=24 << 20),
+               dict(tree=dict(nb=256, a=4, low="greedy", high="greedy"), mhi=4000, nhi=400, budget=96 << 20)]
+
+
+@pytest.mark.parametrize("case", SERVE_CASES, ids=["nb64-greedy", "nb256-ts4-greedy"])
+def test_served_results_equal_lone_solves(cuda, case):
     import torch
 
     import paper_1110_1553_amd as h
     from paper_1110_1553_amd import serve
 
     n_req = 60
-    m, n = inputs.request_shapes(n_req, 9, mlo=64, mhi=2000, nlo=8, nhi=160)
+    m, n = inputs.request_shapes(n_req, 9, mlo=64, mhi=case["mhi"], nlo=8, nhi=case["nhi"])
     gaps = inputs.arrival_gaps(n_req, 3000.0, 10)
     arrivals = np.cumsum(gaps)
-    say("serving %d requests over %.1f ms" % (n_req, arrivals[-1] * 1e3))
-    params = h.make_params(nb=64, low="greedy")
+    say("serving %d requests over %.1f ms, %s" % (n_req, arrivals[-1] * 1e3, case["tree"]))
+    params = h.make_params(**case["tree"])
     As = [inputs.gaussian(int(a), int(b), 900 + q) for q, (a, b) in enumerate(zip(m, n))]
     Bs = [inputs.gaussian(int(a), 1, 1900 + q) for q, a in enumerate(m)]
     dev = lambda X: h.colmajor(torch.from_numpy(np.ascontiguousarray(X)).cuda())  # noqa: E731
     reqs = [serve.Request(q, dev(As[q]), dev(Bs[q]), float(arrivals[q])) for q in range(n_req)]
-    # a budget of 24 MiB in two slots forces several batches
-    be = serve.GpuBackend(params, 24 << 20, max_inflight=2, exec_=h.make_exec(spin_limit=4000000))
+    # the budget in two slots forces several batches
+    be = serve.GpuBackend(params, case["budget"], max_inflight=2, exec_=h.make_exec(spin_limit=4000000))
     sch = serve.Scheduler(be)
     lat = sch.run(reqs)
     torch.cuda.synchronize()
