@@ -182,6 +182,10 @@ __device__ __forceinline__ void stores_done() { __builtin_amdgcn_s_waitcnt(0); }
 // wave-uniform, `off` the element offset of this lane (< 2^28).
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 constexpr int kCoherent = 16;  // cache policy bit: coherent at device scope
+// FP64 tile loads and stores: device-coherent and non-temporal (a hint;
+// with it the FP64 factorizations took 0.3-1% less time, the FP32 one 1.7%
+// more, so float accesses keep the plain coherent policy).
+constexpr int kTileAccess = kCoherent | 2;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
   // the base is wave-uniform by construction; say so, so that it lives in
@@ -200,14 +204,14 @@ template <typename E>
 __device__ __forceinline__ V2<E> bload2(__amdgpu_buffer_rsrc_t r, int off);
 template <>
 __device__ __forceinline__ d2 bload2<double>(__amdgpu_buffer_rsrc_t r, int off) {
-  return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off * 8, 0, kCoherent));
+  return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off * 8, 0, kTileAccess));
 }
 template <>
 __device__ __forceinline__ f2 bload2<float>(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(r, off * 4, 0, kCoherent));
 }
 __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, int off, d2 v) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off * 8, 0, kCoherent);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off * 8, 0, kTileAccess);
 }
 // One element at byte offset voff + soff (soff a wave-uniform constant),
 // plain (non-coherent) load: for kernels that read what an earlier launch
