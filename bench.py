@@ -41,9 +41,9 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # copy-in kernel of known size.  Valid only for the kernel source they were
 # measured on (first 16 hex digits of the SHA-256 of csrc/kernels.hip).
 TRAFFIC = {
-    "tall-hqr": {"kernels_sha256": "674598165883f069", "read": 39.80e9, "write": 21.33e9,
+    "tall-hqr": {"kernels_sha256": "577485b801b01c3a", "read": 39.80e9, "write": 21.33e9,
                  "profile": "profiles/persistent_kernel_tall-hqr.md"},
-    "square-flat": {"kernels_sha256": "674598165883f069", "read": 176.60e9, "write": 94.48e9,
+    "square-flat": {"kernels_sha256": "577485b801b01c3a", "read": 176.60e9, "write": 94.48e9,
                     "profile": "profiles/persistent_kernel_square-flat.md"},
 }
 

@@ -9,7 +9,7 @@
 // I - V T V^T is applied to the rest of the tile(s) with FP64 MFMA
 // (v_mfma_f64_16x16x4f64).  The update kernels apply the 16-column panels of
 // a finished factorization one after another with the V panels staged
-// through double-buffered LDS.
+// through LDS.
 //
 // Work split inside a workgroup (512 threads, 8 waves, one workgroup per CU
 // so two waves share each SIMD): every wave owns a strip of 16 matrix
@@ -19,12 +19,14 @@
 // LDS.  An update task covers 128 columns (8 strips).  The column loop of
 // the panel kernels runs on waves 0-3 (16 columns x 16 lanes).
 //
-// Register layout of an accumulator block (16 rows x 16 columns): lane l,
-// element r holds MFMA row (l / 16) + 4 r, column l % 16.  Matrix rows are
-// assigned to MFMA rows through pi(x) = 4 (x % 4) + x / 4, so that element r
-// of lane l is matrix row 4 (l / 16) + r: each lane holds 4 consecutive rows
-// of one column and loads/stores them with two 16-byte accesses.  The same
-// permutation is applied to the reflector index of W = V^T C.
+// Register layout of an FP64 accumulator block (16 rows x 16 columns): lane
+// l, element r holds MFMA row (l / 16) + 4 r, column l % 16.  Matrix rows
+// are assigned to MFMA rows so that element r of lane l is matrix row
+// 2 g + (r & 1) + 8 (r >> 1), g = l / 16: the four lane groups of a column
+// cover its 16 rows as two contiguous 64-byte halves, each lane moving its
+// rows with two 16-byte accesses (arow, roff).  The same permutation is
+// applied to the reflector index of W = V^T C.  Update tasks stage their V
+// panels two at a time (one barrier per pair).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
